@@ -1,0 +1,52 @@
+// Reference CPU implementation of look-up-table generation and image correction.
+//
+// TEST INFRASTRUCTURE ONLY. This code is the oracle that the GPU library is
+// checked against. Only the test suite, the smoke check and the benchmark's
+// CPU-baseline leg may load it. It shares no source, header, table or helper
+// with the GPU library, and the GPU library never calls it.
+//
+// The paper (Banerjee & Dave, §I) names "LUT generation and image correction"
+// as a typical compute-heavy task but gives no formula for it. The definition
+// fixed here, and used by both sides, is:
+//
+//   LUT build, for every band b, detector d and level v in [0, L):
+//     lut[b][d][v] = clamp(round_half_away(P_bd(v)), 0, L-1)
+//     P_bd(v) = ((a3*v + a2)*v + a1)*v + a0        (Horner, binary64, no FMA)
+//     with a0..a3 = coeffs[b][d][0..3] (ascending degree; quadratics use a3 = 0)
+//   Clamp happens in binary64 before the integer conversion:
+//     NaN, negatives, -0 and -Inf give 0;  values >= L-1 (and +Inf) give L-1.
+//
+//   Correction (per pixel gather), band-sequential push-broom image [B][N][D]:
+//     out[b][n][d] = lut[b][d][min(dn[b][n][d], L-1)]
+//
+// Parity pins (independent of this file) live in tests/test_oracle_pins.py.
+#pragma once
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+// One LUT entry: binary64 Horner over a[0..3] at integer level v, then
+// round half away from zero and clamp to [0, levels-1].
+uint16_t oracle_lut_entry(const double* a, int32_t v, int32_t levels);
+
+// lut[(b*D + d)*L + v] for all b < bands, d < detectors, v < levels.
+// coeffs is [bands][detectors][4] binary64.
+void oracle_lut_build(const double* coeffs, int32_t bands, int32_t detectors,
+                      int32_t levels, uint16_t* lut);
+
+// out[(b*N + n)*D + d] = lut[(b*D + d)*L + min(dn[(b*N + n)*D + d], L-1)].
+void oracle_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines,
+                    int32_t detectors, int32_t bands, int32_t levels,
+                    uint16_t* out);
+
+// Brute force: the same result as oracle_correct(oracle_lut_build(...)), but
+// every pixel evaluates its polynomial directly, without any table.
+void oracle_pixel(const double* coeffs, const uint16_t* dn, int64_t lines,
+                  int32_t detectors, int32_t bands, int32_t levels,
+                  uint16_t* out);
+
+#ifdef __cplusplus
+}
+#endif

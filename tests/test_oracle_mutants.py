@@ -1,0 +1,69 @@
+"""Plant plausible mistakes in a copy of the oracle source (on the CPU) and
+check that at least one pin catches each of them. This is what makes the
+pins worth trusting: a dropped term, a wrong sign, a transposed index, the
+wrong rounding rule or a fused multiply-add all fail."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import build as obuild
+import pins
+
+SRC = os.path.join(os.path.dirname(obuild.__file__), "oracle.cpp")
+
+MUTANTS = {
+    "drop_a2": [("acc = acc + a[2];", "acc = acc + 0.0;")],
+    "drop_a3": [("double acc = a[3];", "double acc = 0.0;")],
+    "sign_a0": [("acc = acc + a[0];", "acc = acc - a[0];")],
+    "swap_a1_a2": [("acc = acc + a[2];", "acc = acc + a[@];"),
+                   ("acc = acc + a[1];", "acc = acc + a[2];"),
+                   ("acc = acc + a[@];", "acc = acc + a[1];")],
+    "floor_plus_half": [("std::round(acc)", "std::floor(acc + 0.5)")],
+    "half_to_even": [("std::round(acc)", "std::nearbyint(acc)")],
+    "fused_last_step": [("acc = acc * x;\n    acc = acc + a[0];", "acc = std::fma(acc, x, a[0]);")],
+    "single_precision": [("double acc = a[3];", "float acc = (float)a[3];")],
+    "clamp_top_off_by_one": [("if (r >= top) return (uint16_t)(levels - 1);",
+                              "if (r >= top) return (uint16_t)(levels);")],
+    "mask_not_min": [("if (v > top) v = top;", "v = (uint16_t)(v & top);")],
+    "lut_ignores_band": [("out[pix] = lut[row * (size_t)levels + (size_t)v];",
+                          "out[pix] = lut[(size_t)d * (size_t)levels + (size_t)v];")],
+    "image_stride_swap": [
+        ("const size_t pix = ((size_t)b * (size_t)lines + (size_t)n) * (size_t)detectors\n"
+         "                                   + (size_t)d;\n                uint16_t v = dn[pix];",
+         "const size_t pix = ((size_t)b * (size_t)detectors + (size_t)d) * (size_t)lines\n"
+         "                                   + (size_t)n;\n                uint16_t v = dn[pix];")],
+    "lut_transposed": [("lut[row * (size_t)levels + (size_t)v] = oracle_lut_entry",
+                        "lut[(size_t)v * (size_t)bands * (size_t)detectors + row] = oracle_lut_entry")],
+    "level_off_by_one": [("const double x = (double)v;", "const double x = (double)(v + 1);")],
+}
+
+
+def _saturation_pin(o):
+    L = 1024
+    lut = (np.arange(2 * L, dtype=np.int64).reshape(1, 2, L) % 997).astype(np.uint16)
+    dn = np.array([[[1023, 1024], [2047, 65535]]], dtype=np.uint16)
+    out = o.correct(dn, lut)
+    assert out.tolist() == [[[lut[0, 0, 1023], lut[0, 1, 1023]],
+                             [lut[0, 0, 1023], lut[0, 1, 1023]]]]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    src = open(SRC).read()
+    for old, new in MUTANTS[name]:
+        assert src.count(old) == 1, f"mutation site not unique for {name}: {old!r}"
+        src = src.replace(old, new)
+    path = tmp_path / "oracle_mutant.cpp"
+    path.write_text(src)
+    lib = obuild.build(src=str(path), out=str(tmp_path / "liboracle_mutant.so"))
+    o = oracle.Oracle(lib)
+    caught = []
+    for pin in pins.ALL_PINS + [_saturation_pin]:
+        try:
+            pin(o)
+        except AssertionError:
+            caught.append(pin.__name__)
+            break
+    assert caught, f"mutant {name} passed every pin"
