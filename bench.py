@@ -1,0 +1,201 @@
+"""Benchmark: LUT build + image correction on one MI355X.
+
+One step = rc_lut_build + rc_correct over the 4-band x 12000-line x 12000-detector
+scene (L = 1024, quadratic coefficients), inputs resident in HBM. Prints one
+JSON line with whole-step Gpix/s, the correction kernel's roofline position
+(algorithmic bytes / HIP-event duration vs 8 TB/s), the CPU oracle's rate on
+this host, and whether the GPU output is bit-identical to the oracle's.
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU time spent timing the oracle")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("device_ops.h", "lut_apply.hip", "api.cpp"):
+        with open(os.path.join(ROOT, "paper_1505_05655_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload_name, algo_bytes):
+    """HBM bytes per correction launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(PROFILES, f"lut_apply_{workload_name}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the path shards by band/detector strip with no exchange, see the design notes.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_1505_05655_amd as rc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = gen.workload(args.workload)
+    t0 = time.time()
+    coeffs = s.coeffs()
+    dn = s.dn()
+    gen_s = time.time() - t0
+    print(f"[bench] workload {s.name}: {s.pixels / 1e6:.1f} Mpix generated in {gen_s:.1f}s",
+          file=sys.stderr, flush=True)
+
+    c_t = torch.from_numpy(coeffs).to(dev)
+    dn_t = torch.from_numpy(dn.view(np.int16)).to(dev)
+    lut_t = torch.empty((s.bands, s.detectors, s.levels), dtype=torch.int16, device=dev)
+    out_t = torch.empty_like(dn_t)
+    stream = torch.cuda.Stream(device=dev)  # default priority
+    plan, tuned = rc.rc_plan_for(s.lines, s.detectors, s.bands, s.levels, dn_t, out_t)
+
+    def step():
+        rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
+        rc.rc_correct(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, stream)
+
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # Timed region: K whole steps, events around each kernel on the launch stream.
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
+        ev[k][1].record(stream)
+        rc.rc_correct(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, stream)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    build_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps)]
+    apply_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps)]
+    ms_per_step = wall * 1e3 / args.steps
+
+    px = s.pixels
+    lut_bytes = s.bands * s.detectors * s.levels * 2
+    apply_bytes = 4 * px + lut_bytes                      # 2 B read + 2 B written per pixel + LUT once
+    build_bytes = lut_bytes + s.bands * s.detectors * 32  # LUT written + coefficients read
+    apply_avg = statistics.mean(apply_ms)
+    achieved = apply_bytes / (apply_avg * 1e-3) / 1e9
+    value = px / (ms_per_step * 1e-3) / 1e9
+
+    bit_exact = None
+    cpu = None
+    if not args.no_cpu_baseline or not args.no_verify:
+        import oracle
+        o = oracle.get()
+        # The oracle is single-threaded; time whole passes of the same step
+        # (LUT build + correction) until at least --cpu-seconds have elapsed.
+        want = np.empty_like(dn)
+        passes, c0 = 0, time.perf_counter()
+        while True:
+            want_lut = o.lut_build(coeffs, s.levels)
+            o.correct(dn, want_lut, out=want)
+            passes += 1
+            el = time.perf_counter() - c0
+            if args.no_cpu_baseline or el >= args.cpu_seconds:
+                break
+        if not args.no_cpu_baseline:
+            cpu = {"value": round(px * passes / el / 1e9, 4), "unit": "Gpix/s", "cores": 1,
+                   "kind": "oracle",
+                   "sample": f"{passes} full pass(es) of the same step (LUT build + correction "
+                             f"of all {px} pixels), {el:.1f}s, single-threaded, host "
+                             f"{cpu_model()} with {os.cpu_count()} logical CPUs"}
+        if not args.no_verify:
+            got = out_t.cpu().numpy().view(np.uint16)
+            got_lut = lut_t.cpu().numpy().view(np.uint16)
+            bit_exact = bool(np.array_equal(got, want) and np.array_equal(got_lut, want_lut))
+
+    props = torch.cuda.get_device_properties(dev)
+    line = {
+        "metric": "corrected Gpix/s (LUT build + correction per step), bit-exact vs CPU oracle",
+        "value": round(value, 3),
+        "unit": "Gpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16 gather (LUT build in f64)",
+        "data": "synthetic, seeded",
+        "config": {"workload": s.name, "bands": s.bands, "lines": s.lines,
+                   "detectors": s.detectors, "levels": s.levels, "seed": s.seed,
+                   "plan": plan.as_dict(), "plan_tuned": tuned},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(s.name, apply_bytes),
+                     "kernel": "lut_apply", "algorithmic_bytes": apply_bytes},
+        "cpu_baseline": cpu,
+        "bit_exact": bit_exact,
+        "kernels": {
+            "lut_apply_ms": {"mean": round(apply_avg, 4), "min": round(min(apply_ms), 4),
+                             "median": round(statistics.median(apply_ms), 4)},
+            "lut_apply_gpix_s": round(px / (apply_avg * 1e-3) / 1e9, 2),
+            "lut_build_ms": {"mean": round(statistics.mean(build_ms), 4),
+                             "min": round(min(build_ms), 4)},
+            "lut_build_gb_s": round(build_bytes / (statistics.mean(build_ms) * 1e-3) / 1e9, 1),
+        },
+        "device": {"name": props.name, "cus": props.multi_processor_count,
+                   "hbm_gib": round(props.total_memory / 2 ** 30, 1),
+                   "arch": getattr(props, "gcnArchName", "")},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+/*
+ * rc.h - radiometric LUT correction on MI355X (gfx950): C ABI of librc.so.
+ *
+ * The paper (Banerjee & Dave, "GPGPU Based Parallelized Client-Server
+ * Framework for Providing High Performance Computation Support", §I) names
+ * look-up-table generation and image correction as a typical task that a
+ * client submits with its data to a GPU server and gets back. It gives no
+ * formula; this library fixes the operation as:
+ *
+ *   LUT build   lut[b][d][v] = clamp(round_half_away(P_bd(v)), 0, L-1),  v in [0, L)
+ *               P_bd(v) = ((a3 v + a2) v + a1) v + a0 in binary64, evaluated in
+ *               exactly this order with one rounding per operation (no FMA).
+ *               The clamp happens in binary64 before the integer conversion:
+ *               NaN, -0, negatives and -Inf give 0; values >= L-1 and +Inf give L-1.
+ *   Correction  out[b][n][d] = lut[b][d][min(dn[b][n][d], L-1)]   (a pure gather)
+ *
+ * Layouts (all dense, row-major, no padding):
+ *   coeffs  [bands][detectors][RC_NCOEF] binary64, ascending degree a0..a3;
+ *           quadratics pass a3 = 0 (bit-identical to quadratic Horner).
+ *   lut     [bands][detectors][levels] uint16.
+ *   dn, out [bands][lines][detectors] uint16, band-sequential push-broom
+ *           images: one line is one read-out of the detector array.
+ *
+ * Common rules for every entry point:
+ *   - Pointers are device pointers (hipMalloc / torch CUDA tensors) unless a
+ *     function says host. The caller owns them. The plain entry points
+ *     (rc_lut_build, rc_correct, rc_correct_plan) allocate nothing and never
+ *     synchronise, so they can be captured in a hipGraph.
+ *   - Arguments are validated on the host before anything is enqueued; on
+ *     RC_EINVAL nothing was enqueued. A dimension of 0 is a valid empty call
+ *     (RC_OK, nothing enqueued, pointers may then be NULL); negative
+ *     dimensions are invalid.
+ *   - A failed launch returns RC_EHIP; rc_last_hip_error() gives the
+ *     hipError_t (thread-local). Faults inside a kernel surface at the
+ *     caller's next synchronisation of `stream`.
+ *   - `stream` orders the work; 0 is the null stream.
+ *   - Every call is bit-exact against the CPU definition above.
+ */
+#ifndef RC_H_
+#define RC_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RC_OK = 0,
+    RC_EINVAL = 1,   /* bad argument; nothing enqueued */
+    RC_ENOMEM = 2,   /* an allocation failed or a job can never fit */
+    RC_EHIP = 3,     /* a HIP runtime call failed; see rc_last_hip_error() */
+    RC_EBUSY = 4,    /* resource temporarily unavailable (retry) */
+    RC_ECLOSED = 5   /* the server is shut down */
+} rc_status;
+
+#define RC_NCOEF 4
+#define RC_LEVELS_MIN 2
+#define RC_LEVELS_MAX 65536
+
+/* Human-readable name of a status code (static storage). */
+const char* rc_status_str(rc_status s);
+
+/* hipError_t of the last RC_EHIP returned on this thread (0 if none). */
+int32_t rc_last_hip_error(void);
+
+/*
+ * LUT build (§I: "Look-up Table (LUT) generation").
+ *   coeffs    device, [bands][detectors][4] binary64, 8-byte aligned.
+ *   levels    L in [RC_LEVELS_MIN, RC_LEVELS_MAX].
+ *   lut       device, [bands][detectors][levels] uint16, 2-byte aligned; written.
+ * Errors: RC_EINVAL for NULL pointers with a non-empty size, negative dims,
+ * levels out of range, misalignment, byte counts overflowing int64, or lut
+ * overlapping coeffs.
+ */
+rc_status rc_lut_build(const double* coeffs, int32_t bands, int32_t detectors, int32_t levels,
+                       uint16_t* lut, hipStream_t stream);
+
+/*
+ * Image correction (§I: "Image Correction") with the library's plan for this
+ * shape (a tuned plan from the plan cache if one matches, else the default).
+ *   dn        device, [bands][lines][detectors] uint16, 2-byte aligned; read.
+ *   lut       device, [bands][detectors][levels] uint16, built by rc_lut_build.
+ *   out       device, same shape as dn; written. out == dn (in place) is
+ *             allowed; any other overlap of out with dn or lut is RC_EINVAL.
+ * Deviation from the two-call outline (dn, lut, lines, detectors, bands, out,
+ * stream): `levels` is inserted after `bands` because it is the LUT row pitch.
+ */
+rc_status rc_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                     int32_t bands, int32_t levels, uint16_t* out, hipStream_t stream);
+
+/* ---- execution plans (launch shape of the correction kernel) ---------------------------- */
+
+typedef enum {
+    RC_PATH_LDS = 0, /* strip LUTs staged in LDS, level-major */
+    RC_PATH_L2 = 1   /* gathers from the global LUT, tiles ordered to stay L2-resident */
+} rc_path;
+
+typedef struct {
+    int32_t path;        /* rc_path */
+    int32_t strip;       /* W: detectors per strip, power of two in [1, 1024] */
+    int32_t vec;         /* pixels per lane per line: 1, 2 or 4 */
+    int32_t threads;     /* workgroup size: 256, 512 or 1024 */
+    int32_t unroll;      /* lines in flight per lane: 4, 8 or 16 */
+    int32_t chunk_lines; /* lines per tile, >= 1 */
+    int32_t xcd_remap;   /* 1: place neighbouring tiles on the same XCD */
+    int32_t nontemporal; /* 1: streaming (non-temporal) image loads and stores */
+} rc_plan;
+
+/*
+ * The plan rc_correct uses for this shape (tuned if the plan cache has one,
+ * else the default heuristic). Host only; enqueues nothing.
+ * `source` (may be NULL) receives 1 for a tuned plan, 0 for the default.
+ */
+rc_status rc_plan_for(int64_t lines, int32_t detectors, int32_t bands, int32_t levels,
+                      const uint16_t* dn, const uint16_t* out, rc_plan* plan, int32_t* source);
+
+/*
+ * rc_correct with an explicit plan. Checks the plan against the shape and the
+ * device (LDS size, alignment needed by `vec`): RC_EINVAL if it cannot run.
+ * Used by the autotuner and by tests that force a path.
+ */
+rc_status rc_correct_plan(const uint16_t* dn, const uint16_t* lut, int64_t lines,
+                          int32_t detectors, int32_t bands, int32_t levels, uint16_t* out,
+                          const rc_plan* plan, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RC_H_ */

@@ -1,0 +1,172 @@
+"""Python binding of librc.so: radiometric LUT build and image correction on MI355X.
+
+Argument marshalling only. Every step runs in the HIP kernels of librc.so;
+PyTorch provides device memory (tensors) and streams. There is no CPU
+fallback: importing this package fails if the library has not been built.
+
+Functions named like the C ABI (``rc_lut_build``, ``rc_correct``,
+``rc_correct_plan``, ``rc_plan_for``) take device tensors or raw device
+pointers (ints) plus the same sizes as the C functions. ``lut_build`` and
+``correct`` are shape-checked conveniences on top of them.
+
+uint16 data is carried in torch.int16 (or torch.uint16) tensors: only the
+bits matter and no arithmetic is done on them in Python.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it first (python __graft_entry__.py build, or "
+        "python paper_1505_05655_amd/build.py). There is no CPU fallback.")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+RC_OK, RC_EINVAL, RC_ENOMEM, RC_EHIP, RC_EBUSY, RC_ECLOSED = range(6)
+RC_PATH_LDS, RC_PATH_L2 = 0, 1
+RC_NCOEF = 4
+RC_LEVELS_MIN, RC_LEVELS_MAX = 2, 65536
+
+
+class RcError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.rc_status_str(status).decode()
+        if status == RC_EHIP:
+            msg += f" (hipError {_lib.rc_last_hip_error()})"
+        super().__init__(f"{where}: {msg}")
+
+
+class Plan(ctypes.Structure):
+    """Launch shape of the correction kernel (mirrors rc_plan)."""
+    _fields_ = [("path", ctypes.c_int32), ("strip", ctypes.c_int32), ("vec", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("chunk_lines", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("nontemporal", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(**{k: int(d[k]) for k, _ in cls._fields_})
+
+    def __repr__(self):
+        return f"Plan({self.as_dict()})"
+
+
+_vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+_lib.rc_status_str.argtypes = [ctypes.c_int]
+_lib.rc_status_str.restype = ctypes.c_char_p
+_lib.rc_last_hip_error.argtypes = []
+_lib.rc_last_hip_error.restype = _i32
+_lib.rc_lut_build.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp]
+_lib.rc_lut_build.restype = ctypes.c_int
+_lib.rc_correct.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp]
+_lib.rc_correct.restype = ctypes.c_int
+_lib.rc_correct_plan.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, ctypes.POINTER(Plan), _vp]
+_lib.rc_correct_plan.restype = ctypes.c_int
+_lib.rc_plan_for.argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, ctypes.POINTER(Plan),
+                             ctypes.POINTER(_i32)]
+_lib.rc_plan_for.restype = ctypes.c_int
+
+
+def lib():
+    """The loaded ctypes library (for tests that call the C ABI directly)."""
+    return _lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, torch.Tensor):
+        if x.numel() and not x.is_cuda:
+            raise ValueError("expected a device tensor")
+        if not x.is_contiguous():
+            raise ValueError("expected a contiguous tensor")
+        return x.data_ptr() if x.numel() else None
+    raise TypeError(f"expected a tensor or an int pointer, got {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(st, where):
+    if st != RC_OK:
+        raise RcError(st, where)
+
+
+# --- same-name wrappers of the C ABI ------------------------------------------------------
+
+def rc_lut_build(coeffs, bands, detectors, levels, lut, stream=None):
+    _check(_lib.rc_lut_build(_ptr(coeffs), bands, detectors, levels, _ptr(lut), _stream(stream)),
+           "rc_lut_build")
+
+
+def rc_correct(dn, lut, lines, detectors, bands, levels, out, stream=None):
+    _check(_lib.rc_correct(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out),
+                           _stream(stream)), "rc_correct")
+
+
+def rc_correct_plan(dn, lut, lines, detectors, bands, levels, out, plan, stream=None):
+    _check(_lib.rc_correct_plan(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out),
+                                ctypes.byref(plan), _stream(stream)), "rc_correct_plan")
+
+
+def rc_plan_for(lines, detectors, bands, levels, dn=None, out=None):
+    """(Plan, tuned?) that rc_correct would use for this shape and these pointers."""
+    p = Plan()
+    src = _i32(0)
+    _check(_lib.rc_plan_for(lines, detectors, bands, levels, _ptr(dn), _ptr(out), ctypes.byref(p),
+                            ctypes.byref(src)), "rc_plan_for")
+    return p, bool(src.value)
+
+
+# --- shape-checked conveniences -------------------------------------------------------------
+
+def _u16(t):
+    return t.dtype in (torch.int16, getattr(torch, "uint16", torch.int16))
+
+
+def lut_build(coeffs, levels, lut=None, stream=None):
+    """coeffs: float64 device tensor [B, D, 4] -> LUT int16/uint16 device tensor [B, D, L]."""
+    if coeffs.dtype != torch.float64 or coeffs.dim() != 3 or coeffs.shape[2] != RC_NCOEF:
+        raise ValueError("coeffs must be float64 [bands, detectors, 4]")
+    B, D, _ = coeffs.shape
+    if lut is None:
+        lut = torch.empty((B, D, levels), dtype=torch.int16, device=coeffs.device)
+    if not _u16(lut) or tuple(lut.shape) != (B, D, levels):
+        raise ValueError("lut must be 16-bit [bands, detectors, levels]")
+    rc_lut_build(coeffs, B, D, levels, lut, stream)
+    return lut
+
+
+def correct(dn, lut, out=None, plan=None, stream=None):
+    """dn: 16-bit device tensor [B, N, D]; lut: [B, D, L] -> out [B, N, D]."""
+    if not _u16(dn) or not _u16(lut) or dn.dim() != 3 or lut.dim() != 3:
+        raise ValueError("dn [B, N, D] and lut [B, D, L] must be 16-bit tensors")
+    B, N, D = dn.shape
+    if tuple(lut.shape[:2]) != (B, D):
+        raise ValueError("lut shape does not match dn")
+    L = lut.shape[2]
+    if out is None:
+        out = torch.empty_like(dn)
+    if tuple(out.shape) != tuple(dn.shape) or not _u16(out):
+        raise ValueError("out must match dn")
+    if plan is None:
+        rc_correct(dn, lut, N, D, B, L, out, stream)
+    else:
+        rc_correct_plan(dn, lut, N, D, B, L, out, plan, stream)
+    return out

@@ -1,0 +1,310 @@
+// C-ABI entry points of the plain path: validation, plan choice, launch.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "kernels.h"
+#include "rc.h"
+#include "runtime.h"
+
+namespace rc {
+
+namespace {
+
+thread_local int32_t t_last_hip = 0;
+
+constexpr int kMaxDevices = 64;
+DeviceInfo g_info[kMaxDevices];
+bool g_ready[kMaxDevices];
+std::mutex g_mu;
+
+int ilog2(int64_t x) {
+    int r = 0;
+    while (((int64_t)1 << (r + 1)) <= x) ++r;
+    return r;
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+}  // namespace
+
+rc_status hip_fail(hipError_t e) {
+    t_last_hip = (int32_t)e;
+    return RC_EHIP;
+}
+
+const DeviceInfo* current_device(int* dev_out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        hip_fail(e);
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        hip_fail(hipErrorInvalidDevice);
+        return nullptr;
+    }
+    if (dev_out) *dev_out = dev;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_ready[dev]) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) {
+            hip_fail(e);
+            return nullptr;
+        }
+        DeviceInfo& di = g_info[dev];
+        di.cus = prop.multiProcessorCount;
+        di.lds = prop.sharedMemPerBlock;
+        if (prop.sharedMemPerBlockOptin > di.lds) di.lds = prop.sharedMemPerBlockOptin;
+        di.lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                              : di.lds;
+        di.arch = prop.gcnArchName;
+        const size_t colon = di.arch.find(':');
+        if (colon != std::string::npos) di.arch.resize(colon);
+        di.hbm_bytes = prop.totalGlobalMem;
+        int x = 1;
+        if (hipDeviceGetAttribute(&x, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || x < 1)
+            x = 1;
+        di.xcds = x;
+        e = prepare_apply_kernels(di.lds);
+        if (e != hipSuccess) {
+            hip_fail(e);
+            return nullptr;
+        }
+        g_ready[dev] = true;
+    }
+    return &g_info[dev];
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return na && nb && x < y + nb && y < x + na;
+}
+
+bool mul_ok(int64_t a, int64_t b, int64_t* r) { return !__builtin_mul_overflow(a, b, r); }
+
+int max_vec(const uint16_t* dn, const uint16_t* out, int32_t detectors) {
+    const uintptr_t al = (uintptr_t)dn | (uintptr_t)out;
+    if (detectors % 4 == 0 && (al & 7u) == 0) return 4;
+    if (detectors % 2 == 0 && (al & 3u) == 0) return 2;
+    return 1;
+}
+
+int plan_slots(const rc_plan& plan, size_t lds_bytes, const DeviceInfo& di) {
+    int per_cu = std::max(1, 2048 / std::max(64, (int)plan.threads));
+    if (plan.path == RC_PATH_LDS && lds_bytes) {
+        per_cu = std::min<int>(per_cu, (int)(di.lds_per_cu / lds_bytes));
+    }
+    return std::max(1, per_cu) * std::max(1, di.cus);
+}
+
+// Default launch shape. LDS path: the widest power-of-two strip whose LUT
+// rows fit the workgroup's LDS (W = 64 at L = 1024, W = 16 at L = 4096);
+// the L2 path when fewer than 8 detectors would fit. Two pixels per lane
+// when alignment allows (with a 2^k * 64-entry level pitch, the 32 lanes of
+// a half-wave then read 32 different LDS banks). The line chunk balances
+// the tail of the last wave of tiles against re-staging the LUT per tile.
+void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
+                  const DeviceInfo& di, rc_plan* plan) {
+    rc_plan p;
+    std::memset(&p, 0, sizeof(p));
+    const size_t budget = di.lds ? di.lds : 65536;
+    int W = 256;
+    while (W > 1 && (size_t)W * (size_t)levels * 2 > budget) W >>= 1;
+    const int64_t dcap = std::max<int64_t>(1, (int64_t)1 << (ilog2(detectors) +
+                                                              (is_pow2(detectors) ? 0 : 1)));
+    p.vec = vmax >= 2 ? 2 : 1;
+    if (W >= 8) {
+        p.path = RC_PATH_LDS;
+        p.strip = (int)std::max<int64_t>(p.vec, std::min<int64_t>(W, dcap));
+        p.threads = 1024;
+    } else {
+        p.path = RC_PATH_L2;
+        p.strip = (int)std::max<int64_t>(p.vec, std::min<int64_t>(64, dcap));
+        p.threads = 256;
+    }
+    p.unroll = 8;
+    p.xcd_remap = 1;
+    p.nontemporal = 0;
+
+    const size_t lds_bytes = p.path == RC_PATH_LDS ? (size_t)p.strip * levels * 2 : 0;
+    const int slots = plan_slots(p, lds_bytes, di);
+    const int64_t strips = (detectors + p.strip - 1) / p.strip;
+    const int64_t base = (int64_t)bands * strips;
+    int64_t best_k = 1;
+    double best = -1.0;
+    const int64_t kmax = std::max<int64_t>(1, std::min<int64_t>(64, lines / 16));
+    for (int64_t k = 1; k <= kmax; ++k) {
+        const int64_t ch = (lines + k - 1) / k;
+        const int64_t chunks = (lines + ch - 1) / ch;
+        const int64_t tiles = base * chunks;
+        if (tiles > (int64_t)1 << 22) break;
+        const double waves = (double)tiles / slots;
+        const double eff = waves / std::ceil(waves);
+        const double stage = p.path == RC_PATH_LDS ? (double)levels * 2.0 / ((double)ch * 4.0) : 0;
+        double score = eff / (1.0 + stage);
+        if (p.path == RC_PATH_L2 && chunks < 32 && lines >= 32 * 64) score *= 0.5;
+        if (score > best * 1.0001) {
+            best = score;
+            best_k = k;
+        }
+    }
+    p.chunk_lines = (int32_t)std::min<int64_t>((lines + best_k - 1) / best_k, INT32_MAX);
+    *plan = p;
+}
+
+rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int32_t bands,
+                     int32_t levels, int vmax, const DeviceInfo& di, ApplyParams* p,
+                     size_t* lds_bytes) {
+    if (plan.path != RC_PATH_LDS && plan.path != RC_PATH_L2) return RC_EINVAL;
+    if (!is_pow2(plan.strip) || plan.strip > 1024) return RC_EINVAL;
+    if (plan.vec != 1 && plan.vec != 2 && plan.vec != 4) return RC_EINVAL;
+    if (plan.vec > vmax || plan.strip < plan.vec) return RC_EINVAL;
+    if (plan.threads != 256 && plan.threads != 512 && plan.threads != 1024) return RC_EINVAL;
+    if (plan.unroll != 4 && plan.unroll != 8 && plan.unroll != 16) return RC_EINVAL;
+    if (plan.chunk_lines < 1) return RC_EINVAL;
+    if (plan.strip / plan.vec > plan.threads) return RC_EINVAL;
+    const size_t bytes = plan.path == RC_PATH_LDS ? (size_t)plan.strip * (size_t)levels * 2 : 0;
+    if (bytes > di.lds) return RC_EINVAL;
+    const int64_t strips = (detectors + (int64_t)plan.strip - 1) / plan.strip;
+    const int64_t chunks = (lines + plan.chunk_lines - 1) / plan.chunk_lines;
+    int64_t tiles = 0;
+    if (!mul_ok((int64_t)bands * strips, chunks, &tiles)) return RC_EINVAL;
+    if (tiles * plan.threads >= ((int64_t)1 << 32) || tiles > INT32_MAX) return RC_EINVAL;
+    p->lines = lines;
+    p->detectors = detectors;
+    p->levels = levels;
+    p->bands = bands;
+    p->log_strip = ilog2(plan.strip);
+    p->strips = (int32_t)strips;
+    p->chunks = (int32_t)chunks;
+    p->chunk_lines = plan.chunk_lines;
+    p->ntiles = (int32_t)tiles;
+    p->xcds = plan.xcd_remap ? di.xcds : 1;
+    p->chunk_major = plan.path == RC_PATH_L2 ? 1 : 0;
+    *lds_bytes = bytes;
+    return RC_OK;
+}
+
+namespace {
+
+// Shape and pointer validation shared by rc_correct and rc_correct_plan.
+rc_status validate_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines,
+                           int32_t detectors, int32_t bands, int32_t levels, const uint16_t* out,
+                           bool* empty) {
+    *empty = false;
+    if (lines < 0 || detectors < 0 || bands < 0) return RC_EINVAL;
+    if (levels < RC_LEVELS_MIN || levels > RC_LEVELS_MAX) return RC_EINVAL;
+    int64_t px = 0, lut_n = 0, bytes = 0;
+    if (!mul_ok(lines, detectors, &px) || !mul_ok(px, bands, &px) || !mul_ok(px, 2, &bytes))
+        return RC_EINVAL;
+    if (!mul_ok((int64_t)bands * detectors, levels, &lut_n) || !mul_ok(lut_n, 2, &lut_n))
+        return RC_EINVAL;
+    if (px == 0) {
+        *empty = true;
+        return RC_OK;
+    }
+    if (!dn || !lut || !out) return RC_EINVAL;
+    if (((uintptr_t)dn | (uintptr_t)lut | (uintptr_t)out) & 1u) return RC_EINVAL;
+    if (dn != out && overlaps(dn, (size_t)bytes, out, (size_t)bytes)) return RC_EINVAL;
+    if (overlaps(lut, (size_t)lut_n, out, (size_t)bytes)) return RC_EINVAL;
+    return RC_OK;
+}
+
+rc_status run_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                      int32_t bands, int32_t levels, uint16_t* out, const rc_plan* forced,
+                      hipStream_t stream) {
+    bool empty = false;
+    rc_status st = validate_correct(dn, lut, lines, detectors, bands, levels, out, &empty);
+    if (st != RC_OK || empty) return st;
+    const DeviceInfo* di = current_device();
+    if (!di) return RC_EHIP;
+    const int vmax = max_vec(dn, out, detectors);
+    rc_plan plan;
+    if (forced) {
+        plan = *forced;
+    } else if (!tuned_plan(lines, detectors, bands, levels, vmax, *di, &plan)) {
+        default_plan(lines, detectors, bands, levels, vmax, *di, &plan);
+    }
+    ApplyParams p;
+    size_t lds_bytes = 0;
+    st = check_plan(plan, lines, detectors, bands, levels, vmax, *di, &p, &lds_bytes);
+    if (st != RC_OK) return st;
+    p.dn = dn;
+    p.lut = lut;
+    p.out = out;
+    p.lut_vec = (levels % 8 == 0 && ((uintptr_t)lut & 15u) == 0) ? 1 : 0;
+    hipError_t e = launch_apply(p, plan, lds_bytes, stream);
+    return e == hipSuccess ? RC_OK : hip_fail(e);
+}
+
+}  // namespace
+}  // namespace rc
+
+using namespace rc;
+
+extern "C" {
+
+const char* rc_status_str(rc_status s) {
+    switch (s) {
+        case RC_OK: return "RC_OK";
+        case RC_EINVAL: return "RC_EINVAL: invalid argument";
+        case RC_ENOMEM: return "RC_ENOMEM: out of memory";
+        case RC_EHIP: return "RC_EHIP: HIP runtime error";
+        case RC_EBUSY: return "RC_EBUSY: busy";
+        case RC_ECLOSED: return "RC_ECLOSED: closed";
+    }
+    return "rc_status: unknown";
+}
+
+int32_t rc_last_hip_error(void) { return t_last_hip; }
+
+rc_status rc_lut_build(const double* coeffs, int32_t bands, int32_t detectors, int32_t levels,
+                       uint16_t* lut, hipStream_t stream) {
+    if (bands < 0 || detectors < 0) return RC_EINVAL;
+    if (levels < RC_LEVELS_MIN || levels > RC_LEVELS_MAX) return RC_EINVAL;
+    int64_t rows = 0, entries = 0, cbytes = 0, lbytes = 0;
+    if (!mul_ok(bands, detectors, &rows) || !mul_ok(rows, levels, &entries) ||
+        !mul_ok(entries, 2, &lbytes) || !mul_ok(rows, 32, &cbytes))
+        return RC_EINVAL;
+    if (rows == 0) return RC_OK;
+    if (!coeffs || !lut) return RC_EINVAL;
+    if (((uintptr_t)coeffs & 7u) || ((uintptr_t)lut & 1u)) return RC_EINVAL;
+    if (overlaps(coeffs, (size_t)cbytes, lut, (size_t)lbytes)) return RC_EINVAL;
+    int dev = 0;
+    if (!current_device(&dev)) return RC_EHIP;
+    hipError_t e = launch_lut_build(coeffs, rows, levels, lut, stream);
+    return e == hipSuccess ? RC_OK : hip_fail(e);
+}
+
+rc_status rc_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                     int32_t bands, int32_t levels, uint16_t* out, hipStream_t stream) {
+    return run_correct(dn, lut, lines, detectors, bands, levels, out, nullptr, stream);
+}
+
+rc_status rc_correct_plan(const uint16_t* dn, const uint16_t* lut, int64_t lines,
+                          int32_t detectors, int32_t bands, int32_t levels, uint16_t* out,
+                          const rc_plan* plan, hipStream_t stream) {
+    if (!plan) return RC_EINVAL;
+    return run_correct(dn, lut, lines, detectors, bands, levels, out, plan, stream);
+}
+
+rc_status rc_plan_for(int64_t lines, int32_t detectors, int32_t bands, int32_t levels,
+                      const uint16_t* dn, const uint16_t* out, rc_plan* plan, int32_t* source) {
+    if (!plan || lines <= 0 || detectors <= 0 || bands <= 0) return RC_EINVAL;
+    if (levels < RC_LEVELS_MIN || levels > RC_LEVELS_MAX) return RC_EINVAL;
+    const DeviceInfo* di = current_device();
+    if (!di) return RC_EHIP;
+    const int vmax = max_vec(dn, out, detectors);
+    const bool tuned = tuned_plan(lines, detectors, bands, levels, vmax, *di, plan);
+    if (!tuned) default_plan(lines, detectors, bands, levels, vmax, *di, plan);
+    if (source) *source = tuned ? 1 : 0;
+    return RC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+// Host-visible launch interface of the HIP kernels (internal to librc).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "rc.h"
+
+namespace rc {
+
+// Everything the correction kernel needs to decode a tile id.
+struct ApplyParams {
+    const uint16_t* dn;
+    const uint16_t* lut;
+    uint16_t* out;
+    int64_t lines;       // N
+    int32_t detectors;   // D
+    int32_t levels;      // L
+    int32_t bands;       // B
+    int32_t log_strip;   // log2(W)
+    int32_t strips;      // ceil(D / W)
+    int32_t chunks;      // ceil(N / chunk_lines)
+    int64_t chunk_lines;
+    int32_t ntiles;      // bands * strips * chunks
+    int32_t xcds;        // 0/1: identity tile order, else the XCD count
+    int32_t chunk_major; // 0: strips vary fastest, 1: line chunks vary fastest
+    int32_t lut_vec;     // LUT rows may be staged with 16-byte loads
+};
+
+// lut_build: one thread per 8 consecutive levels of one LUT row.
+hipError_t launch_lut_build(const double* coeffs, int64_t rows, int32_t levels, uint16_t* lut,
+                            hipStream_t stream);
+
+// Correction with the given plan (already validated).
+hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,
+                        hipStream_t stream);
+
+// Raise the dynamic-LDS limit of every correction kernel to `bytes` on the
+// current device (once per device).
+hipError_t prepare_apply_kernels(size_t bytes);
+
+}  // namespace rc

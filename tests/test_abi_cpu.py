@@ -1,0 +1,99 @@
+"""The C-ABI library loads, exports every function include/rc.h declares, and
+rejects bad arguments on the host before touching the GPU. CPU only: no
+compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1505_05655_amd as rc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        for m in re.finditer(r"\b(rc_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("rc_lut_build", "rc_correct", "rc_status_str", "rc_last_hip_error"):
+        assert must in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_symbol_exported(name):
+    assert hasattr(rc.lib(), name), f"librc.so does not export {name}"
+
+
+def test_status_strings():
+    lib = rc.lib()
+    for s in range(6):
+        assert lib.rc_status_str(s).startswith(b"RC_")
+
+
+L = rc.lib()
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("args", [
+    (None, 1, 1, 1024, FAKE),            # NULL coeffs
+    (FAKE, 1, 1, 1024, None),            # NULL lut
+    (FAKE, -1, 1, 1024, FAKE),           # negative bands
+    (FAKE, 1, -5, 1024, FAKE),           # negative detectors
+    (FAKE, 1, 1, 1, FAKE),               # levels < 2
+    (FAKE, 1, 1, 65537, FAKE),           # levels > 65536
+    (FAKE + 4, 1, 1, 1024, FAKE + 64),   # coeffs not 8-byte aligned
+    (FAKE, 1, 1, 1024, FAKE + 4097),     # lut not 2-byte aligned
+    (FAKE, 1, 1, 1024, FAKE + 16),       # lut overlaps coeffs
+    (FAKE, 1 << 30, 1 << 30, 1024, FAKE * 4),  # byte count overflows
+])
+def test_lut_build_rejects(args):
+    assert L.rc_lut_build(*args, None) == rc.RC_EINVAL
+
+
+def test_lut_build_empty_is_noop():
+    assert L.rc_lut_build(None, 0, 5, 1024, None, None) == rc.RC_OK
+    assert L.rc_lut_build(None, 3, 0, 1024, None, None) == rc.RC_OK
+
+
+BIG = 1 << 24
+
+
+@pytest.mark.parametrize("args", [
+    (None, FAKE, 4, 4, 1, 1024, FAKE * 64),         # NULL dn
+    (FAKE, None, 4, 4, 1, 1024, FAKE * 64),         # NULL lut
+    (FAKE, FAKE * 64, 4, 4, 1, 1024, None),         # NULL out
+    (FAKE, FAKE * 64, -1, 4, 1, 1024, FAKE * 128),  # negative lines
+    (FAKE, FAKE * 64, 4, -4, 1, 1024, FAKE * 128),  # negative detectors
+    (FAKE, FAKE * 64, 4, 4, -1, 1024, FAKE * 128),  # negative bands
+    (FAKE, FAKE * 64, 4, 4, 1, 1, FAKE * 128),      # levels < 2
+    (FAKE, FAKE * 64, 4, 4, 1, 70000, FAKE * 128),  # levels > 65536
+    (FAKE + 1, FAKE * 64, 4, 4, 1, 1024, FAKE * 128),   # dn odd address
+    (FAKE, FAKE * 64, 4, 4, 1, 1024, FAKE * 128 + 1),   # out odd address
+    (FAKE, FAKE * 64, 4, 4, 1, 1024, FAKE + 2),     # out partially overlaps dn
+    (FAKE, FAKE * 64, 4, 4, 1, 1024, FAKE * 64 + 8),  # out overlaps lut
+    (FAKE, FAKE * 64, 1 << 40, 1 << 30, 4, 1024, FAKE * 128),  # pixel count overflows
+])
+def test_correct_rejects(args):
+    assert L.rc_correct(*args, None) == rc.RC_EINVAL
+
+
+def test_correct_empty_is_noop():
+    assert L.rc_correct(None, None, 0, 100, 2, 1024, None, None) == rc.RC_OK
+    assert L.rc_correct(None, None, 10, 0, 2, 1024, None, None) == rc.RC_OK
+    assert L.rc_correct(None, None, 10, 100, 0, 1024, None, None) == rc.RC_OK
+
+
+def test_correct_plan_requires_plan():
+    assert L.rc_correct_plan(FAKE, FAKE * 64, 4, 4, 1, 1024, FAKE * 128, None, None) == rc.RC_EINVAL

@@ -1,0 +1,205 @@
+"""GPU path (through the C ABI) against the CPU oracle, bit-exact.
+
+Covers the hand-derived golden entries, the three single-scene workloads at
+full size with the plan the benchmark times, ragged and degenerate shapes,
+every launch-shape knob on both correction paths, in-place correction,
+2-byte-aligned pointers and out-of-bounds write guards."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_1505_05655_amd as rc
+import pins
+from gpu_util import Guarded, dev, to_dev_f64, to_dev_u16, to_host_u16
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.get()
+
+
+def run_case(o, coeffs, dn, levels, plan=None, dn_offset=0, out_offset=0, in_place=False):
+    """Build + correct on the GPU; return (lut, out) on the host and check the
+    guard bands."""
+    B, N, D = dn.shape
+    lut_g = Guarded((B, D, levels))
+    rc.lut_build(to_dev_f64(coeffs), levels, lut=lut_g.t)
+    dn_g = Guarded((B, N, D), offset=dn_offset)
+    dn_g.t.copy_(to_dev_u16(dn))
+    if in_place:
+        out_g = dn_g
+    else:
+        out_g = Guarded((B, N, D), offset=out_offset)
+    rc.correct(dn_g.t, lut_g.t, out=out_g.t, plan=plan)
+    torch.cuda.synchronize()
+    for g in (lut_g, dn_g, out_g):
+        g.check_pads()
+    return lut_g.host(), out_g.host()
+
+
+def expect(o, coeffs, dn, levels):
+    lut = o.lut_build(coeffs, levels)
+    return lut, o.correct(dn, lut)
+
+
+def test_golden_entries():
+    rows = pins.load_round_clamp()
+    for a, levels, v, want, text in rows:
+        lut = rc.lut_build(to_dev_f64(np.array(a).reshape(1, 1, 4)), levels)
+        got = int(to_host_u16(lut)[0, 0, v])
+        assert got == want, f"GPU golden case failed: got {got}: {text}"
+
+
+@pytest.mark.parametrize("w", [0, 1, 2])
+def test_lut_build_workloads(o, w):
+    s = gen.workload(w)
+    coeffs = s.coeffs()
+    lut = to_host_u16(rc.lut_build(to_dev_f64(coeffs), s.levels))
+    assert np.array_equal(lut, o.lut_build(coeffs, s.levels))
+
+
+@pytest.mark.parametrize("levels", [2, 3, 7, 1000, 1023, 1024, 4097, 65536])
+def test_lut_build_levels_and_specials(o, levels):
+    rng = np.random.default_rng(levels)
+    coeffs = np.zeros((2, 5, 4))
+    coeffs[..., 0] = rng.normal(0, levels / 64, size=(2, 5))
+    coeffs[..., 1] = rng.uniform(0.5, 1.5, size=(2, 5))
+    coeffs[..., 2] = rng.normal(0, 2.0 / levels, size=(2, 5))
+    coeffs[..., 3] = rng.normal(0, 1.0 / levels ** 2, size=(2, 5))
+    coeffs[0, 0] = [np.nan, 1, 0, 0]
+    coeffs[0, 1] = [np.inf, 0, 0, 0]
+    coeffs[0, 2] = [-np.inf, 0, 0, 0]
+    coeffs[1, 0] = [0.5, 1, 0, 0]
+    coeffs[1, 1] = [0, 1, 0, 0]
+    want = o.lut_build(coeffs, levels)
+    # Aligned and misaligned (2-byte) LUT pointers take different store paths.
+    for off in (0, 1):
+        g = Guarded((2, 5, levels), offset=off)
+        rc.lut_build(to_dev_f64(coeffs), levels, lut=g.t)
+        torch.cuda.synchronize()
+        g.check_pads()
+        assert np.array_equal(g.host(), want), f"L={levels} offset={off}"
+
+
+SHAPES = [
+    (1, 1, 1, 2),          # single pixel, smallest L
+    (3, 7, 37, 1024),      # tiny ragged
+    (2, 333, 1000, 1024),  # ragged strip and line tails
+    (1, 1030, 1031, 1024),  # odd detector count -> one pixel per lane
+    (1, 1030, 1030, 1024),  # 2 mod 4 detector count
+    (2, 517, 130, 4096),   # 12-bit LUT, narrow strips
+    (1, 64, 12000, 1024),  # wide line, few lines
+    (1, 3, 5, 65536),      # 16-bit LUT -> L2 path
+    (2, 100, 300, 3),      # three levels
+    (1, 2000, 8, 1000),    # narrower than a strip, non-power-of-two L
+    (4, 50, 70, 1024),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_correct_shapes(o, shape):
+    B, N, D, L = shape
+    coeffs, dn = pins.tiny_case(sum(shape), B, N, D, L)
+    want_lut, want = expect(o, coeffs, dn, L)
+    lut, out = run_case(o, coeffs, dn, L)
+    assert np.array_equal(lut, want_lut)
+    assert np.array_equal(out, want)
+
+
+def plans_for(N, D, L):
+    plans = []
+    for path, strip, vec, threads, unroll, xcd, nt in itertools.product(
+            (rc.RC_PATH_LDS, rc.RC_PATH_L2), (8, 16, 64), (1, 2, 4), (256, 1024), (4, 16),
+            (0, 1), (0, 1)):
+        if path == rc.RC_PATH_LDS and strip * L * 2 > 160 * 1024:
+            continue
+        if (strip + vec + threads + unroll + xcd + nt + path) % 3:  # thin the grid
+            continue
+        for chunk in (1, 37, N):
+            plans.append(rc.Plan(path=path, strip=strip, vec=vec, threads=threads, unroll=unroll,
+                                 chunk_lines=chunk, xcd_remap=xcd, nontemporal=nt))
+    return plans
+
+
+@pytest.mark.parametrize("shape", [(2, 301, 1000, 1024), (1, 211, 600, 4096)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_correct_forced_plans(o, shape):
+    B, N, D, L = shape
+    coeffs, dn = pins.tiny_case(7, B, N, D, L)
+    want_lut, want = expect(o, coeffs, dn, L)
+    lut_t = rc.lut_build(to_dev_f64(coeffs), L)
+    dn_t = to_dev_u16(dn)
+    plans = plans_for(N, D, L)
+    assert len(plans) > 20
+    for plan in plans:
+        out = Guarded((B, N, D))
+        rc.correct(dn_t, lut_t, out=out.t, plan=plan)
+        torch.cuda.synchronize()
+        out.check_pads()
+        assert np.array_equal(out.host(), want), f"plan {plan}"
+
+
+def test_plan_rejected_when_lds_too_small():
+    dn = torch.zeros((1, 4, 64), dtype=torch.int16, device=dev())
+    lut = torch.zeros((1, 64, 4096), dtype=torch.int16, device=dev())
+    bad = rc.Plan(path=rc.RC_PATH_LDS, strip=64, vec=2, threads=256, unroll=4, chunk_lines=4,
+                  xcd_remap=0, nontemporal=0)  # 64 x 4096 x 2 B = 512 KiB of LDS
+    with pytest.raises(rc.RcError) as e:
+        rc.correct(dn, lut, plan=bad)
+    assert e.value.status == rc.RC_EINVAL
+
+
+def test_in_place(o):
+    B, N, D, L = 2, 129, 200, 1024
+    coeffs, dn = pins.tiny_case(5, B, N, D, L)
+    _, want = expect(o, coeffs, dn, L)
+    _, out = run_case(o, coeffs, dn, L, in_place=True)
+    assert np.array_equal(out, want)
+
+
+@pytest.mark.parametrize("offs", [(1, 0), (0, 1), (1, 1), (2, 3)])
+def test_misaligned_images(o, offs):
+    B, N, D, L = 2, 77, 96, 1024
+    coeffs, dn = pins.tiny_case(9, B, N, D, L)
+    _, want = expect(o, coeffs, dn, L)
+    _, out = run_case(o, coeffs, dn, L, dn_offset=offs[0], out_offset=offs[1])
+    assert np.array_equal(out, want)
+
+
+def test_saturating_dn(o):
+    B, N, D, L = 1, 16, 64, 1024
+    coeffs, _ = pins.tiny_case(3, B, N, D, L)
+    dn = np.full((B, N, D), 65535, dtype=np.uint16)
+    dn[0, ::2] = 1024
+    dn[0, 1::4] = 1023
+    _, want = expect(o, coeffs, dn, L)
+    _, out = run_case(o, coeffs, dn, L)
+    assert np.array_equal(out, want)
+
+
+@pytest.mark.parametrize("w", [0, 1, 2])
+def test_workload_full_size(o, w):
+    """Full-size single-scene workloads with the plan rc_correct picks (the one
+    the benchmark times): every output pixel compared with the oracle."""
+    s = gen.workload(w)
+    print(f"workload {w}: {s.name}", flush=True)
+    coeffs = s.coeffs()
+    dn = s.dn()
+    want_lut = o.lut_build(coeffs, s.levels)
+    want = o.correct(dn, want_lut)
+    c_t = to_dev_f64(coeffs)
+    dn_t = to_dev_u16(dn)
+    lut_t = rc.lut_build(c_t, s.levels)
+    out_t = torch.empty_like(dn_t)
+    rc.correct(dn_t, lut_t, out=out_t)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host_u16(lut_t), want_lut)
+    out = to_host_u16(out_t)
+    bad = np.count_nonzero(out != want)
+    assert bad == 0, f"{bad} pixels differ"
