@@ -34,7 +34,22 @@ def parse():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time spent timing the oracle")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 4 device-to-device copies of MIB MiB (hardware counter "
+                         "calibration: a plain copy kernel of known size) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib * (1 << 20) // 2
+    src = torch.ones(n, dtype=torch.int16, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_each_way": n * 2, "launches": 4}))
 
 
 def kernel_source_hash():
@@ -71,6 +86,9 @@ def cpu_model():
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the path shards by band/detector strip with no exchange, see the design notes.",

@@ -93,8 +93,11 @@ rc_status rc_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, int
 /* ---- execution plans (launch shape of the correction kernel) ---------------------------- */
 
 typedef enum {
-    RC_PATH_LDS = 0, /* strip LUTs staged in LDS, level-major */
-    RC_PATH_L2 = 1   /* gathers from the global LUT, tiles ordered to stay L2-resident */
+    RC_PATH_LDS = 0,    /* strip LUT rows staged in LDS as 16-bit entries, level-major */
+    RC_PATH_L2 = 1,     /* gathers from the global LUT, tiles ordered to stay L2-resident */
+    RC_PATH_PACKED = 2  /* strip LUT rows staged in LDS as 32-level blocks of a 16-bit base
+                           plus 2-bit steps (2.5 bits/entry, exact); a tile whose rows have a
+                           step outside 0..3 gathers from the global LUT instead */
 } rc_path;
 
 typedef struct {
@@ -124,6 +127,31 @@ rc_status rc_plan_for(int64_t lines, int32_t detectors, int32_t bands, int32_t l
 rc_status rc_correct_plan(const uint16_t* dn, const uint16_t* lut, int64_t lines,
                           int32_t detectors, int32_t bands, int32_t levels, uint16_t* out,
                           const rc_plan* plan, hipStream_t stream);
+
+/* ---- autotuner and plan cache --------------------------------------------------------- */
+
+/*
+ * Times candidate plans for this shape on the caller's buffers (dn, lut as
+ * for rc_correct; `out` is overwritten, must differ from dn) and records the
+ * fastest in the in-memory plan cache under the shape class
+ * (arch, CU count, levels, ceil(log2 detectors), ceil(log2 lines), bands,
+ * usable vector width). effort 0 = reduced candidate set, 1 = full sweep.
+ * `best` / `best_us` (may be NULL) receive the winner and its mean time in us.
+ * Synchronises `stream`; not capturable. Errors: RC_EINVAL, RC_EHIP.
+ */
+rc_status rc_tune(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                  int32_t bands, int32_t levels, uint16_t* out, int32_t effort, rc_plan* best,
+                  float* best_us, hipStream_t stream);
+
+/* Persist / reload the plan cache (one JSON object per line). path NULL means
+ * $RC_TUNE_CACHE, else tune_cache.json next to librc.so, which is also the
+ * file loaded on first use. Return the number of entries, or -1 on I/O error
+ * (a failed load leaves the cache empty). Host only. */
+int32_t rc_tune_save(const char* path);
+int32_t rc_tune_load(const char* path);
+/* Empty the in-memory cache (rc_correct then uses default plans). */
+void rc_tune_clear(void);
+int32_t rc_tune_count(void);
 
 #ifdef __cplusplus
 }

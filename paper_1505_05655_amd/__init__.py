@@ -28,7 +28,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_EHIP, RC_EBUSY, RC_ECLOSED = range(6)
-RC_PATH_LDS, RC_PATH_L2 = 0, 1
+RC_PATH_LDS, RC_PATH_L2, RC_PATH_PACKED = 0, 1, 2
 RC_NCOEF = 4
 RC_LEVELS_MIN, RC_LEVELS_MAX = 2, 65536
 
@@ -74,6 +74,17 @@ _lib.rc_correct_plan.restype = ctypes.c_int
 _lib.rc_plan_for.argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, ctypes.POINTER(Plan),
                              ctypes.POINTER(_i32)]
 _lib.rc_plan_for.restype = ctypes.c_int
+_lib.rc_tune.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _i32, ctypes.POINTER(Plan),
+                         ctypes.POINTER(ctypes.c_float), _vp]
+_lib.rc_tune.restype = ctypes.c_int
+_lib.rc_tune_save.argtypes = [ctypes.c_char_p]
+_lib.rc_tune_save.restype = _i32
+_lib.rc_tune_load.argtypes = [ctypes.c_char_p]
+_lib.rc_tune_load.restype = _i32
+_lib.rc_tune_clear.argtypes = []
+_lib.rc_tune_clear.restype = None
+_lib.rc_tune_count.argtypes = []
+_lib.rc_tune_count.restype = _i32
 
 
 def lib():
@@ -132,6 +143,34 @@ def rc_plan_for(lines, detectors, bands, levels, dn=None, out=None):
     _check(_lib.rc_plan_for(lines, detectors, bands, levels, _ptr(dn), _ptr(out), ctypes.byref(p),
                             ctypes.byref(src)), "rc_plan_for")
     return p, bool(src.value)
+
+
+def rc_tune(dn, lut, lines, detectors, bands, levels, out, effort=0, stream=None):
+    """Autotune the correction plan for this shape; returns (Plan, microseconds)."""
+    p = Plan()
+    us = ctypes.c_float(0)
+    _check(_lib.rc_tune(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out), effort,
+                        ctypes.byref(p), ctypes.byref(us), _stream(stream)), "rc_tune")
+    return p, float(us.value)
+
+
+def rc_tune_save(path=None):
+    n = _lib.rc_tune_save(path.encode() if path else None)
+    if n < 0:
+        raise OSError(f"rc_tune_save failed for {path!r}")
+    return n
+
+
+def rc_tune_load(path=None):
+    return _lib.rc_tune_load(path.encode() if path else None)
+
+
+def rc_tune_clear():
+    _lib.rc_tune_clear()
+
+
+def rc_tune_count():
+    return _lib.rc_tune_count()
 
 
 # --- shape-checked conveniences -------------------------------------------------------------

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "device_ops.h"
 #include "kernels.h"
 #include "rc.h"
 #include "runtime.h"
@@ -71,11 +72,13 @@ const DeviceInfo* current_device(int* dev_out) {
         if (hipDeviceGetAttribute(&x, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || x < 1)
             x = 1;
         di.xcds = x;
-        e = prepare_apply_kernels(di.lds);
+        size_t usable = 0;
+        e = prepare_apply_kernels(di.lds, &usable);
         if (e != hipSuccess) {
             hip_fail(e);
             return nullptr;
         }
+        di.lds = usable;
         g_ready[dev] = true;
     }
     return &g_info[dev];
@@ -97,42 +100,50 @@ int max_vec(const uint16_t* dn, const uint16_t* out, int32_t detectors) {
 
 int plan_slots(const rc_plan& plan, size_t lds_bytes, const DeviceInfo& di) {
     int per_cu = std::max(1, 2048 / std::max(64, (int)plan.threads));
-    if (plan.path == RC_PATH_LDS && lds_bytes) {
+    if (plan.path != RC_PATH_L2 && lds_bytes) {
         per_cu = std::min<int>(per_cu, (int)(di.lds_per_cu / lds_bytes));
     }
     return std::max(1, per_cu) * std::max(1, di.cus);
 }
 
-// Default launch shape. LDS path: the widest power-of-two strip whose LUT
-// rows fit the workgroup's LDS (W = 64 at L = 1024, W = 16 at L = 4096);
-// the L2 path when fewer than 8 detectors would fit. Two pixels per lane
-// when alignment allows (with a 2^k * 64-entry level pitch, the 32 lanes of
-// a half-wave then read 32 different LDS banks). The line chunk balances
-// the tail of the last wave of tiles against re-staging the LUT per tile.
+size_t plan_lds_bytes(int path, int strip, int levels) {
+    if (path == RC_PATH_LDS) return (size_t)strip * (size_t)levels * 2;
+    if (path == RC_PATH_PACKED) return packed_lds_bytes(strip, levels);
+    return 0;
+}
+
+// Default launch shape (no tuning). Strips are made as wide as an 80 KiB LDS
+// tile allows (two workgroups per CU), because measured HBM throughput of a
+// strip-shaped stream grows with the strip width: packed LDS rows for
+// L >= 512 (W = 256 at L = 1024, W = 64 at L = 4096), raw 16-bit rows for
+// smaller L, and the L2 path when fewer than 16 detectors would fit. Four
+// pixels per lane when alignment allows. The line chunk balances the tail of
+// the last wave of tiles against re-staging the LUT strip per tile.
 void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
                   const DeviceInfo& di, rc_plan* plan) {
     rc_plan p;
     std::memset(&p, 0, sizeof(p));
-    const size_t budget = di.lds ? di.lds : 65536;
+    const size_t budget = std::min<size_t>(di.lds ? di.lds : 65536, 80 * 1024);
+    const int path_lds = levels >= 512 ? RC_PATH_PACKED : RC_PATH_LDS;
     int W = 256;
-    while (W > 1 && (size_t)W * (size_t)levels * 2 > budget) W >>= 1;
+    while (W > 1 && plan_lds_bytes(path_lds, W, levels) > budget) W >>= 1;
     const int64_t dcap = std::max<int64_t>(1, (int64_t)1 << (ilog2(detectors) +
                                                               (is_pow2(detectors) ? 0 : 1)));
-    p.vec = vmax >= 2 ? 2 : 1;
-    if (W >= 8) {
-        p.path = RC_PATH_LDS;
+    p.vec = vmax >= 4 ? 4 : vmax;
+    if (W >= 16) {
+        p.path = path_lds;
         p.strip = (int)std::max<int64_t>(p.vec, std::min<int64_t>(W, dcap));
-        p.threads = 1024;
     } else {
         p.path = RC_PATH_L2;
         p.strip = (int)std::max<int64_t>(p.vec, std::min<int64_t>(64, dcap));
-        p.threads = 256;
     }
-    p.unroll = 8;
+    p.threads = 256;
+    while (p.strip / p.vec > p.threads) p.threads *= 2;
+    p.unroll = p.vec == 4 ? 4 : 8;
     p.xcd_remap = 1;
     p.nontemporal = 0;
 
-    const size_t lds_bytes = p.path == RC_PATH_LDS ? (size_t)p.strip * levels * 2 : 0;
+    const size_t lds_bytes = plan_lds_bytes(p.path, p.strip, levels);
     const int slots = plan_slots(p, lds_bytes, di);
     const int64_t strips = (detectors + p.strip - 1) / p.strip;
     const int64_t base = (int64_t)bands * strips;
@@ -146,7 +157,7 @@ void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t level
         if (tiles > (int64_t)1 << 22) break;
         const double waves = (double)tiles / slots;
         const double eff = waves / std::ceil(waves);
-        const double stage = p.path == RC_PATH_LDS ? (double)levels * 2.0 / ((double)ch * 4.0) : 0;
+        const double stage = p.path != RC_PATH_L2 ? (double)levels * 2.0 / ((double)ch * 4.0) : 0;
         double score = eff / (1.0 + stage);
         if (p.path == RC_PATH_L2 && chunks < 32 && lines >= 32 * 64) score *= 0.5;
         if (score > best * 1.0001) {
@@ -161,7 +172,8 @@ void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t level
 rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int32_t bands,
                      int32_t levels, int vmax, const DeviceInfo& di, ApplyParams* p,
                      size_t* lds_bytes) {
-    if (plan.path != RC_PATH_LDS && plan.path != RC_PATH_L2) return RC_EINVAL;
+    if (plan.path != RC_PATH_LDS && plan.path != RC_PATH_L2 && plan.path != RC_PATH_PACKED)
+        return RC_EINVAL;
     if (!is_pow2(plan.strip) || plan.strip > 1024) return RC_EINVAL;
     if (plan.vec != 1 && plan.vec != 2 && plan.vec != 4) return RC_EINVAL;
     if (plan.vec > vmax || plan.strip < plan.vec) return RC_EINVAL;
@@ -169,7 +181,7 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
     if (plan.unroll != 4 && plan.unroll != 8 && plan.unroll != 16) return RC_EINVAL;
     if (plan.chunk_lines < 1) return RC_EINVAL;
     if (plan.strip / plan.vec > plan.threads) return RC_EINVAL;
-    const size_t bytes = plan.path == RC_PATH_LDS ? (size_t)plan.strip * (size_t)levels * 2 : 0;
+    const size_t bytes = plan_lds_bytes(plan.path, plan.strip, levels);
     if (bytes > di.lds) return RC_EINVAL;
     const int64_t strips = (detectors + (int64_t)plan.strip - 1) / plan.strip;
     const int64_t chunks = (lines + plan.chunk_lines - 1) / plan.chunk_lines;

@@ -35,8 +35,9 @@ hipError_t launch_lut_build(const double* coeffs, int64_t rows, int32_t levels, 
 hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,
                         hipStream_t stream);
 
-// Raise the dynamic-LDS limit of every correction kernel to `bytes` on the
-// current device (once per device).
-hipError_t prepare_apply_kernels(size_t bytes);
+// Raise the dynamic-LDS limit of every correction kernel on the current
+// device (once per device) as far as `bytes` of LDS per workgroup allows;
+// `usable` receives the dynamic LDS every kernel can then launch with.
+hipError_t prepare_apply_kernels(size_t bytes, size_t* usable);
 
 }  // namespace rc

@@ -1,18 +1,19 @@
 // Correction kernel (§I "Image Correction"): out[b][n][d] = lut[b][d][min(dn, L-1)].
 //
 // One workgroup per tile (band, strip of W detectors, chunk of lines). The
-// LDS path stages the strip's W LUT rows into LDS level-major and streams
-// the chunk's lines through coalesced 16-bit-element vector loads/stores;
-// the L2 path gathers straight from the global LUT and orders tiles so that
-// the CUs of one XCD share a strip whose LUT rows stay in that XCD's L2.
+// raw LDS path stages the strip's W LUT rows into LDS level-major; the packed
+// LDS path stages them as 2.5-bit step codes so strips are 6.4x wider; both
+// then stream the chunk's lines through coalesced vector loads/stores. The
+// L2 path gathers straight from the global LUT and orders tiles so that the
+// CUs of one XCD share a strip whose LUT rows stay in that XCD's L2.
 #include "device_ops.h"
 #include "kernels.h"
 
 namespace rc {
 
-template <int VEC, int UNROLL, bool NTH, bool LDS>
+template <int VEC, int UNROLL, bool NTH, int MODE>
 __global__ __launch_bounds__(1024) void k_apply(ApplyParams p) {
-    extern __shared__ uint16_t smem[];
+    extern __shared__ __align__(16) unsigned char smem[];
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x, p.xcds);
     int s, c, b;
     if (p.chunk_major) {
@@ -31,25 +32,28 @@ __global__ __launch_bounds__(1024) void k_apply(ApplyParams p) {
     const int weff = min(W, p.detectors - d0);
     const int64_t n0 = (int64_t)c * p.chunk_lines;
     const int64_t n1 = min(p.lines, n0 + p.chunk_lines);
-    apply_tile<VEC, UNROLL, NTH, LDS>(p.dn, p.lut, p.out, p.lines, p.detectors, p.levels,
-                                      p.log_strip, b, d0, weff, n0, n1, smem, p.lut_vec != 0);
+    apply_tile<VEC, UNROLL, NTH, MODE>(p.dn, p.lut, p.out, p.lines, p.detectors, p.levels,
+                                       p.log_strip, b, d0, weff, n0, n1, smem, p.lut_vec != 0);
 }
 
 typedef void (*ApplyKernel)(ApplyParams);
 
 namespace {
 
+// row[nontemporal * 3 + mode], mode = rc_path value (raw LDS, L2, packed LDS)
 template <int VEC, int UNROLL>
 void fill_row(ApplyKernel* row) {
-    row[0] = k_apply<VEC, UNROLL, false, false>;
-    row[1] = k_apply<VEC, UNROLL, false, true>;
-    row[2] = k_apply<VEC, UNROLL, true, false>;
-    row[3] = k_apply<VEC, UNROLL, true, true>;
+    row[0] = k_apply<VEC, UNROLL, false, kRaw>;
+    row[1] = k_apply<VEC, UNROLL, false, kGlobal>;
+    row[2] = k_apply<VEC, UNROLL, false, kPacked>;
+    row[3] = k_apply<VEC, UNROLL, true, kRaw>;
+    row[4] = k_apply<VEC, UNROLL, true, kGlobal>;
+    row[5] = k_apply<VEC, UNROLL, true, kPacked>;
 }
 
-// table[vec index][unroll index][nontemporal * 2 + lds]
+// table[vec index][unroll index][nontemporal * 3 + mode]
 struct Table {
-    ApplyKernel k[3][3][4];
+    ApplyKernel k[3][3][6];
     Table() {
         fill_row<1, 4>(k[0][0]);
         fill_row<1, 8>(k[0][1]);
@@ -73,26 +77,41 @@ int unroll_index(int u) { return u == 4 ? 0 : (u == 8 ? 1 : 2); }
 
 }  // namespace
 
-hipError_t prepare_apply_kernels(size_t bytes) {
+hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
+    // A kernel's dynamic LDS limit is the CU's LDS minus its own static LDS
+    // (e.g. the word __syncthreads_or reduces through).
     const Table& t = table();
+    size_t worst_static = 0;
     for (int v = 0; v < 3; ++v)
         for (int u = 0; u < 3; ++u)
-            for (int h = 0; h < 2; ++h) {
-                hipError_t e = hipFuncSetAttribute((const void*)t.k[v][u][h * 2 + 1],
+            for (int m = 0; m < 6; ++m) {
+                if (m % 3 == kGlobal) continue;
+                hipFuncAttributes attr;
+                hipError_t e = hipFuncGetAttributes(&attr, (const void*)t.k[v][u][m]);
+                if (e != hipSuccess) return e;
+                worst_static = attr.sharedSizeBytes > worst_static ? attr.sharedSizeBytes
+                                                                   : worst_static;
+            }
+    const size_t dyn = bytes > worst_static ? bytes - worst_static : 0;
+    for (int v = 0; v < 3; ++v)
+        for (int u = 0; u < 3; ++u)
+            for (int m = 0; m < 6; ++m) {
+                if (m % 3 == kGlobal) continue;
+                hipError_t e = hipFuncSetAttribute((const void*)t.k[v][u][m],
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)bytes);
+                                                   (int)dyn);
                 if (e != hipSuccess) return e;
             }
+    *usable = dyn;
     return hipSuccess;
 }
 
 hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,
                         hipStream_t stream) {
-    const bool lds = plan.path == RC_PATH_LDS;
     ApplyKernel k = table().k[vec_index(plan.vec)][unroll_index(plan.unroll)]
-                             [(plan.nontemporal ? 2 : 0) + (lds ? 1 : 0)];
+                             [(plan.nontemporal ? 3 : 0) + plan.path];
     hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3((unsigned)plan.threads),
-                       lds ? lds_bytes : 0, stream, p);
+                       plan.path == RC_PATH_L2 ? 0 : lds_bytes, stream, p);
     return hipGetLastError();
 }
 

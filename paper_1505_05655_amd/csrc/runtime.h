@@ -40,6 +40,9 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
                      int32_t levels, int vmax, const DeviceInfo& di, ApplyParams* p,
                      size_t* lds_bytes);
 
+// LDS bytes a plan's tile needs (0 for the L2 path).
+size_t plan_lds_bytes(int path, int strip, int levels);
+
 // Concurrent workgroups of one plan on the whole device.
 int plan_slots(const rc_plan& plan, size_t lds_bytes, const DeviceInfo& di);
 

@@ -1,10 +1,347 @@
-// Plan cache lookup (autotuner results).
+// Autotuner and plan cache for the correction kernel.
+//
+// rc_tune times candidate launch shapes (path, strip width, pixels per lane,
+// workgroup size, unroll, line chunking, XCD remap, non-temporal hints) on
+// the caller's buffers with HIP events and keeps the fastest per shape
+// class. Shape class = (arch, CU count, levels, ceil(log2 detectors),
+// ceil(log2 lines), bands, largest usable vector width). Line chunking is
+// stored as a chunk count, so one entry serves every line count of its
+// class. The cache persists as one JSON object per line; rc_correct consults
+// it (host only, no synchronisation) and falls back to the default plan.
+#include <dlfcn.h>
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "rc.h"
 #include "runtime.h"
 
 namespace rc {
 
-bool tuned_plan(int64_t, int32_t, int32_t, int32_t, int, const DeviceInfo&, rc_plan*) {
-    return false;
+namespace {
+
+struct Entry {
+    std::string arch;
+    int cus = 0;
+    int levels = 0;
+    int dclass = 0;
+    int nclass = 0;
+    int bands = 0;
+    int vmax = 0;
+    rc_plan plan{};
+    int chunks = 1;  // line chunks per strip (chunk_lines = ceil(lines / chunks))
+    double us = 0.0;
+};
+
+std::mutex g_mu;
+std::vector<Entry> g_cache;
+bool g_loaded = false;
+
+int clog2(int64_t x) {
+    int r = 0;
+    while (((int64_t)1 << r) < x) ++r;
+    return r;
 }
 
+std::string default_path() {
+    const char* env = std::getenv("RC_TUNE_CACHE");
+    if (env && *env) return env;
+    Dl_info info;
+    if (dladdr((void*)&default_path, &info) && info.dli_fname) {
+        std::string p = info.dli_fname;
+        const size_t slash = p.rfind('/');
+        p = slash == std::string::npos ? std::string(".") : p.substr(0, slash);
+        return p + "/tune_cache.json";
+    }
+    return "tune_cache.json";
+}
+
+// Minimal reader for the flat JSON objects written by save_locked().
+bool get_num(const std::string& line, const char* key, double* out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t at = line.find(k);
+    if (at == std::string::npos) return false;
+    *out = std::strtod(line.c_str() + at + k.size(), nullptr);
+    return true;
+}
+
+bool get_str(const std::string& line, const char* key, std::string* out) {
+    const std::string k = std::string("\"") + key + "\":\"";
+    const size_t at = line.find(k);
+    if (at == std::string::npos) return false;
+    const size_t end = line.find('"', at + k.size());
+    if (end == std::string::npos) return false;
+    *out = line.substr(at + k.size(), end - at - k.size());
+    return true;
+}
+
+bool parse_entry(const std::string& line, Entry* e) {
+    double v[16];
+    const char* keys[] = {"cus", "levels", "dclass", "nclass", "bands", "vmax", "path", "strip",
+                          "vec", "threads", "unroll", "chunks", "xcd_remap", "nontemporal", "us"};
+    for (int i = 0; i < 15; ++i)
+        if (!get_num(line, keys[i], &v[i])) return false;
+    if (!get_str(line, "arch", &e->arch)) return false;
+    e->cus = (int)v[0];
+    e->levels = (int)v[1];
+    e->dclass = (int)v[2];
+    e->nclass = (int)v[3];
+    e->bands = (int)v[4];
+    e->vmax = (int)v[5];
+    e->plan.path = (int32_t)v[6];
+    e->plan.strip = (int32_t)v[7];
+    e->plan.vec = (int32_t)v[8];
+    e->plan.threads = (int32_t)v[9];
+    e->plan.unroll = (int32_t)v[10];
+    e->chunks = std::max(1, (int)v[11]);
+    e->plan.xcd_remap = (int32_t)v[12];
+    e->plan.nontemporal = (int32_t)v[13];
+    e->us = v[14];
+    return true;
+}
+
+int load_locked(const std::string& path) {
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return -1;
+    std::vector<Entry> got;
+    char buf[1024];
+    while (std::fgets(buf, sizeof buf, f)) {
+        Entry e;
+        if (parse_entry(buf, &e)) got.push_back(e);
+    }
+    std::fclose(f);
+    g_cache = got;
+    return (int)got.size();
+}
+
+void ensure_loaded_locked() {
+    if (g_loaded) return;
+    g_loaded = true;
+    load_locked(default_path());
+}
+
+int save_locked(const std::string& path) {
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return -1;
+    for (const Entry& e : g_cache) {
+        std::fprintf(f,
+                     "{\"arch\":\"%s\",\"cus\":%d,\"levels\":%d,\"dclass\":%d,\"nclass\":%d,"
+                     "\"bands\":%d,\"vmax\":%d,\"path\":%d,\"strip\":%d,\"vec\":%d,"
+                     "\"threads\":%d,\"unroll\":%d,\"chunks\":%d,\"xcd_remap\":%d,"
+                     "\"nontemporal\":%d,\"us\":%.3f}\n",
+                     e.arch.c_str(), e.cus, e.levels, e.dclass, e.nclass, e.bands, e.vmax,
+                     e.plan.path, e.plan.strip, e.plan.vec, e.plan.threads, e.plan.unroll,
+                     e.chunks, e.plan.xcd_remap, e.plan.nontemporal, e.us);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) return -1;
+    return (int)g_cache.size();
+}
+
+Entry key_of(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
+             const DeviceInfo& di) {
+    Entry k;
+    k.arch = di.arch;
+    k.cus = di.cus;
+    k.levels = levels;
+    k.dclass = clog2(detectors);
+    k.nclass = clog2(lines);
+    k.bands = bands;
+    k.vmax = vmax;
+    return k;
+}
+
+bool same_class(const Entry& a, const Entry& b) {
+    return a.arch == b.arch && a.cus == b.cus && a.levels == b.levels && a.dclass == b.dclass &&
+           a.nclass == b.nclass && a.bands == b.bands && a.vmax == b.vmax;
+}
+
+int chunk_count(int64_t lines, int32_t chunk_lines) {
+    return (int)std::min<int64_t>(INT32_MAX, (lines + chunk_lines - 1) / chunk_lines);
+}
+
+}  // namespace
+
+bool tuned_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
+                const DeviceInfo& di, rc_plan* plan) {
+    const Entry k = key_of(lines, detectors, bands, levels, vmax, di);
+    rc_plan found;
+    int chunks = 1;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ensure_loaded_locked();
+        auto it = std::find_if(g_cache.begin(), g_cache.end(),
+                               [&](const Entry& e) { return same_class(e, k); });
+        if (it == g_cache.end()) return false;
+        found = it->plan;
+        chunks = it->chunks;
+    }
+    found.chunk_lines = (int32_t)std::max<int64_t>(1, (lines + chunks - 1) / chunks);
+    ApplyParams p;
+    size_t lds = 0;
+    if (check_plan(found, lines, detectors, bands, levels, vmax, di, &p, &lds) != RC_OK)
+        return false;
+    *plan = found;
+    return true;
+}
+
+namespace {
+
+std::vector<rc_plan> candidates(int64_t lines, int32_t detectors, int32_t bands, int32_t levels,
+                                int vmax, const DeviceInfo& di, int effort) {
+    std::vector<rc_plan> out;
+    rc_plan def;
+    default_plan(lines, detectors, bands, levels, vmax, di, &def);
+    out.push_back(def);
+    const int64_t dcap = (int64_t)1 << clog2(std::max(detectors, 1));
+    const int vecs[] = {1, 2, 4};
+    const int threads_all[] = {256, 512, 1024};
+    const int unrolls[] = {4, 8, 16};
+    const int ks[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int path = 0; path < 3; ++path) {
+        for (int W = 8; W <= 256; W *= 2) {
+            if (path != RC_PATH_L2 && plan_lds_bytes(path, W, levels) > di.lds) continue;
+            if (path == RC_PATH_L2 && (W < 32 || W > 128)) continue;
+            if (W > std::max<int64_t>(dcap, 8)) continue;
+            for (int vec : vecs) {
+                if (vec > vmax || W < vec) continue;
+                if (effort == 0 && vec != std::min(vmax, 4) && vec != std::min(vmax, 2)) continue;
+                for (int threads : threads_all) {
+                    if (W / vec > threads) continue;
+                    if (path == RC_PATH_L2 && threads == 512) continue;
+                    for (int unroll : unrolls) {
+                        if (effort == 0 && unroll == 4) continue;
+                        for (int xcd = 0; xcd < 2; ++xcd) {
+                            if (effort == 0 && xcd == 0) continue;
+                            if (path == RC_PATH_L2 && xcd == 0) continue;
+                            for (int nt = 0; nt < 2; ++nt) {
+                                std::vector<int> klist;
+                                if (path == RC_PATH_L2) {
+                                    klist = {32, 64};
+                                } else {
+                                    klist.assign(std::begin(ks), std::end(ks));
+                                }
+                                for (int k : klist) {
+                                    if (k > lines) continue;
+                                    rc_plan p;
+                                    std::memset(&p, 0, sizeof p);
+                                    p.path = path;
+                                    p.strip = W;
+                                    p.vec = vec;
+                                    p.threads = threads;
+                                    p.unroll = unroll;
+                                    p.xcd_remap = xcd;
+                                    p.nontemporal = nt;
+                                    p.chunk_lines = (int32_t)((lines + k - 1) / k);
+                                    out.push_back(p);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return out;
+}
+
+}  // namespace
 }  // namespace rc
+
+using namespace rc;
+
+extern "C" {
+
+rc_status rc_tune(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                  int32_t bands, int32_t levels, uint16_t* out, int32_t effort, rc_plan* best,
+                  float* best_us, hipStream_t stream) {
+    if (lines <= 0 || detectors <= 0 || bands <= 0) return RC_EINVAL;
+    if (levels < RC_LEVELS_MIN || levels > RC_LEVELS_MAX) return RC_EINVAL;
+    if (!dn || !lut || !out || dn == out) return RC_EINVAL;
+    const DeviceInfo* di = current_device();
+    if (!di) return RC_EHIP;
+    const int vmax = max_vec(dn, out, detectors);
+    std::vector<rc_plan> cands = candidates(lines, detectors, bands, levels, vmax, *di, effort);
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(e);
+    }
+    const int reps = 3;
+    float best_t = 1e30f;
+    rc_plan best_p = cands[0];
+    rc_status st = RC_OK;
+    for (const rc_plan& p : cands) {
+        if (rc_correct_plan(dn, lut, lines, detectors, bands, levels, out, &p, stream) != RC_OK)
+            continue;  // not runnable for this shape/device
+        float t = 0.f;
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
+        for (int r = 0; r < reps; ++r)
+            rc_correct_plan(dn, lut, lines, detectors, bands, levels, out, &p, stream);
+        if ((e = hipEventRecord(e1, stream)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) break;
+        t *= 1000.f / reps;
+        if (t < best_t) {
+            best_t = t;
+            best_p = p;
+        }
+    }
+    if (e != hipSuccess) st = hip_fail(e);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != RC_OK) return st;
+    if (best) *best = best_p;
+    if (best_us) *best_us = best_t;
+    Entry ent = key_of(lines, detectors, bands, levels, vmax, *di);
+    ent.plan = best_p;
+    ent.chunks = chunk_count(lines, best_p.chunk_lines);
+    ent.us = best_t;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_loaded_locked();
+    auto it = std::find_if(g_cache.begin(), g_cache.end(),
+                           [&](const Entry& x) { return same_class(x, ent); });
+    if (it != g_cache.end()) *it = ent;
+    else g_cache.push_back(ent);
+    return RC_OK;
+}
+
+int32_t rc_tune_save(const char* path) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_loaded_locked();
+    return save_locked(path && *path ? path : default_path());
+}
+
+int32_t rc_tune_load(const char* path) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_loaded = true;
+    const int n = load_locked(path && *path ? path : default_path());
+    if (n < 0) g_cache.clear();
+    return n;
+}
+
+void rc_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_loaded = true;
+    g_cache.clear();
+}
+
+int32_t rc_tune_count(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_loaded_locked();
+    return (int32_t)g_cache.size();
+}
+
+}  // extern "C"

@@ -115,11 +115,15 @@ def test_correct_shapes(o, shape):
 def plans_for(N, D, L):
     plans = []
     for path, strip, vec, threads, unroll, xcd, nt in itertools.product(
-            (rc.RC_PATH_LDS, rc.RC_PATH_L2), (8, 16, 64), (1, 2, 4), (256, 1024), (4, 16),
-            (0, 1), (0, 1)):
-        if path == rc.RC_PATH_LDS and strip * L * 2 > 160 * 1024:
+            (rc.RC_PATH_LDS, rc.RC_PATH_L2, rc.RC_PATH_PACKED), (8, 16, 64, 256), (1, 2, 4),
+            (256, 1024), (4, 16), (0, 1), (0, 1)):
+        if path == rc.RC_PATH_LDS and strip * L * 2 > 128 * 1024:
             continue
-        if (strip + vec + threads + unroll + xcd + nt + path) % 3:  # thin the grid
+        if path == rc.RC_PATH_PACKED and (L + 31) // 32 * strip * 10 > 128 * 1024:
+            continue
+        if strip // vec > threads:
+            continue
+        if (strip + vec + threads + unroll + xcd + nt + path) % 4:  # thin the grid
             continue
         for chunk in (1, 37, N):
             plans.append(rc.Plan(path=path, strip=strip, vec=vec, threads=threads, unroll=unroll,
@@ -143,6 +147,71 @@ def test_correct_forced_plans(o, shape):
         torch.cuda.synchronize()
         out.check_pads()
         assert np.array_equal(out.host(), want), f"plan {plan}"
+
+
+PACKED_SHAPES = [(2, 301, 1000, 1024), (1, 77, 333, 1000), (3, 40, 50, 3), (1, 65, 130, 4096),
+                 (1, 9, 64, 33), (2, 31, 520, 2048)]
+
+
+@pytest.mark.parametrize("shape", PACKED_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("packable", [True, False])
+def test_packed_path(o, shape, packable):
+    """Packed LDS tiles: exact for packable rows (steps 0..3), and exact through
+    the global-gather fallback for rows that are not (decreasing or steep)."""
+    B, N, D, L = shape
+    coeffs, dn = pins.tiny_case(L + N, B, N, D, L)
+    rng = np.random.default_rng(L + D)
+    # Gain near 1 and a small curvature: rows rise by 0, 1 or 2 per level.
+    coeffs[..., 0] = rng.normal(0, L / 128, size=(B, D))
+    coeffs[..., 1] = rng.uniform(0.9, 1.1, size=(B, D))
+    coeffs[..., 2] = rng.normal(0, 0.05 / L, size=(B, D))
+    coeffs[..., 3] = 0.0
+    if not packable:
+        coeffs[0, D // 2] = [L - 1, -1.0, 0, 0]  # one decreasing row in band 0
+        coeffs[-1, 0] = [0, 5.0, 0, 0]           # one steep row (steps of 5) in the last band
+    want_lut, want = expect(o, coeffs, dn, L)
+    steps = np.diff(want_lut.astype(np.int64), axis=2)
+    assert packable == bool(((steps >= 0) & (steps <= 3)).all())
+    lut_t = rc.lut_build(to_dev_f64(coeffs), L)
+    dn_t = to_dev_u16(dn)
+    for strip, vec, threads, chunk in ((256, 1, 256, N), (64, 2, 512, 7), (16, 1, 1024, 3),
+                                       (128, 2, 256, 1)):
+        if (L + 31) // 32 * strip * 10 > 128 * 1024 or D % vec:
+            continue
+        plan = rc.Plan(path=rc.RC_PATH_PACKED, strip=strip, vec=vec, threads=threads, unroll=8,
+                       chunk_lines=chunk, xcd_remap=1, nontemporal=0)
+        out = Guarded((B, N, D))
+        rc.correct(dn_t, lut_t, out=out.t, plan=plan)
+        torch.cuda.synchronize()
+        out.check_pads()
+        assert np.array_equal(out.host(), want), f"plan {plan}"
+
+
+def test_tuner_roundtrip(tmp_path):
+    """rc_tune picks a plan that reproduces the oracle, stores it in the cache
+    under the shape class, and the cache survives a save/load round trip."""
+    B, N, D, L = 2, 300, 1000, 1024
+    coeffs, dn = pins.tiny_case(1, B, N, D, L)
+    o = oracle.get()
+    _, want = expect(o, coeffs, dn, L)
+    lut_t = rc.lut_build(to_dev_f64(coeffs), L)
+    dn_t = to_dev_u16(dn)
+    out_t = torch.empty_like(dn_t)
+    rc.rc_tune_clear()
+    plan, us = rc.rc_tune(dn_t, lut_t, N, D, B, L, out_t, effort=0)
+    assert us > 0
+    got, tuned = rc.rc_plan_for(N, D, B, L, dn_t, out_t)
+    assert tuned and got.as_dict() == plan.as_dict()
+    path = str(tmp_path / "cache.json")
+    assert rc.rc_tune_save(path) == 1
+    rc.rc_tune_clear()
+    assert not rc.rc_plan_for(N, D, B, L, dn_t, out_t)[1]
+    assert rc.rc_tune_load(path) == 1
+    assert rc.rc_plan_for(N, D, B, L, dn_t, out_t)[1]
+    out = rc.correct(dn_t, lut_t)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host_u16(out), want)
+    rc.rc_tune_load(None)  # back to the packaged cache
 
 
 def test_plan_rejected_when_lds_too_small():
