@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time spent timing the oracle")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-request batch leg")
+    ap.add_argument("--batch-requests", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 4 device-to-device copies of MIB MiB (hardware counter "
                          "calibration: a plain copy kernel of known size) and exit")
@@ -50,6 +52,93 @@ def calibrate_copy(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"calibrate_copy_bytes_each_way": n * 2, "launches": 4}))
+
+
+def bench_batch(args, torch, rc, dev):
+    """Workload 3: uneven requests resident in HBM. Plain path (rc_lut_build +
+    rc_correct per request on one stream) against one batched graph replay."""
+    import gen
+    import oracle
+
+    reqs = gen.batch_requests(args.batch_requests)
+    t0 = time.time()
+    jobs = []
+    for r in reqs:
+        c_t = torch.from_numpy(r.coeffs()).to(dev)
+        d_t = torch.from_numpy(r.dn().view(np.int16)).to(dev)
+        jobs.append((r, c_t, d_t,
+                     torch.empty((r.bands, r.detectors, r.levels), dtype=torch.int16, device=dev),
+                     torch.empty_like(d_t),
+                     torch.empty((r.bands, r.detectors, r.levels), dtype=torch.int16, device=dev),
+                     torch.empty_like(d_t)))
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    px = sum(r.pixels for r in reqs)
+    lut_entries = sum(r.bands * r.detectors * r.levels for r in reqs)
+    algo = 4 * px + 2 * lut_entries + 2 * lut_entries  # image r+w, LUT written + read
+    stream = torch.cuda.Stream(device=dev)
+
+    def plain(sync_each=False):
+        for r, c_t, d_t, lut_p, out_p, _, _ in jobs:
+            rc.rc_lut_build(c_t, r.bands, r.detectors, r.levels, lut_p, stream)
+            rc.rc_correct(d_t, lut_p, r.lines, r.detectors, r.bands, r.levels, out_p, stream)
+            if sync_each:
+                stream.synchronize()
+
+    batch = rc.Batch([(c_t, d_t, lut_b, out_b) for _, c_t, d_t, _, _, lut_b, out_b in jobs])
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - w0) * 1e3 / reps, e0.elapsed_time(e1) / reps
+
+    reps = 3
+    plain_ms, plain_gpu_ms = timed(plain, reps)
+    plain_sync_ms, _ = timed(lambda: plain(True), reps)
+    batch_ms, batch_gpu_ms = timed(lambda: batch.run(stream), reps)
+    same = all(torch.equal(lp, lb) and torch.equal(op, ob)
+               for _, _, _, lp, op, lb, ob in jobs)
+    # Oracle check on a sample: the 6 smallest requests and 2 seeded others.
+    o = oracle.get()
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i].pixels)
+    rng = np.random.default_rng(7)
+    sample = order[:6] + list(rng.choice(order[6:], size=min(2, len(order) - 6), replace=False))
+    oracle_ok = True
+    for i in sample:
+        r, c_t, d_t, _, _, lut_b, out_b = jobs[i]
+        wl = o.lut_build(r.coeffs(), r.levels)
+        w = o.correct(d_t.cpu().numpy().view(np.uint16), wl)
+        oracle_ok &= bool(np.array_equal(lut_b.cpu().numpy().view(np.uint16), wl) and
+                          np.array_equal(out_b.cpu().numpy().view(np.uint16), w))
+    info = batch.info()
+    batch.close()
+    del jobs
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{len(reqs)} uneven requests (lines, detectors in [512, 8192], 1-4 bands, "
+                    "10/12-bit)",
+        "pixels": px, "lut_entries": lut_entries, "algorithmic_bytes": algo,
+        "tiles": info["tiles"], "persistent_workgroups": info["slots"], "graph": bool(info["graph"]),
+        "plain_ms": round(plain_ms, 3), "plain_gpu_ms": round(plain_gpu_ms, 3),
+        "plain_sync_each_ms": round(plain_sync_ms, 3),
+        "batched_ms": round(batch_ms, 3), "batched_gpu_ms": round(batch_gpu_ms, 3),
+        "plain_gpix_s": round(px / (plain_ms * 1e-3) / 1e9, 2),
+        "batched_gpix_s": round(px / (batch_ms * 1e-3) / 1e9, 2),
+        "batched_gb_s": round(algo / (batch_ms * 1e-3) / 1e9, 1),
+        "batched_frac_hbm": round(algo / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "speedup_vs_plain": round(plain_ms / batch_ms, 3),
+        "speedup_vs_plain_sync_each": round(plain_sync_ms / batch_ms, 3),
+        "bit_exact_batched_vs_plain": same,
+        "bit_exact_oracle_sample": oracle_ok, "oracle_sample_requests": [int(i) for i in sample],
+        "setup_s": round(gen_s, 1),
+    }
 
 
 def kernel_source_hash():
@@ -177,6 +266,13 @@ def main():
             got_lut = lut_t.cpu().numpy().view(np.uint16)
             bit_exact = bool(np.array_equal(got, want) and np.array_equal(got_lut, want_lut))
 
+    batch_res = None
+    if not args.no_batch:
+        del dn_t, out_t, lut_t, c_t
+        torch.cuda.empty_cache()
+        print("[bench] batch leg", file=sys.stderr, flush=True)
+        batch_res = bench_batch(args, torch, rc, dev)
+
     props = torch.cuda.get_device_properties(dev)
     line = {
         "metric": "corrected Gpix/s (LUT build + correction per step), bit-exact vs CPU oracle",
@@ -208,6 +304,7 @@ def main():
                              "min": round(min(build_ms), 4)},
             "lut_build_gb_s": round(build_bytes / (statistics.mean(build_ms) * 1e-3) / 1e9, 1),
         },
+        "batch": batch_res,
         "device": {"name": props.name, "cus": props.multi_processor_count,
                    "hbm_gib": round(props.total_memory / 2 ** 30, 1),
                    "arch": getattr(props, "gcnArchName", "")},

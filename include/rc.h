@@ -153,6 +153,63 @@ int32_t rc_tune_load(const char* path);
 void rc_tune_clear(void);
 int32_t rc_tune_count(void);
 
+/* ---- batched execution of many uneven requests ----------------------------------------- */
+
+/*
+ * One correction job, as a client would submit it to the GPU server of the
+ * paper's framework (§II): coefficients in, LUT and corrected image out. All
+ * pointers are device pointers with the layouts and rules of rc_lut_build /
+ * rc_correct (lut is written by the batch).
+ */
+typedef struct {
+    const double* coeffs;  /* [bands][detectors][4] */
+    const uint16_t* dn;    /* [bands][lines][detectors] */
+    uint16_t* lut;         /* [bands][detectors][levels], written */
+    uint16_t* out;         /* [bands][lines][detectors], written; may equal dn */
+    int64_t lines;
+    int32_t detectors;
+    int32_t bands;
+    int32_t levels;
+    int32_t reserved;      /* must be 0 */
+} rc_request;
+
+typedef struct rc_batch rc_batch;
+
+typedef struct {
+    int32_t requests;
+    int32_t tiles;        /* correction tiles in the persistent kernel's queue */
+    int32_t slots;        /* persistent workgroups */
+    int32_t graph;        /* 1 if runs replay a captured hipGraph */
+    int64_t pixels;
+    int64_t lut_entries;
+} rc_batch_stats;
+
+#define RC_BATCH_NO_GRAPH 1 /* flag: launch the two kernels directly on every run */
+
+/*
+ * Plans a batch of n requests on the current device: validates every request
+ * (RC_EINVAL as for the plain calls, and also if an output of one request
+ * overlaps any buffer of another), picks each request's strip shape from the
+ * plan cache (or the default plan), builds the tile queue (longest tiles
+ * first), allocates the batch's small device tables and captures the LUT
+ * build kernel plus the persistent correction kernel into a hipGraph.
+ * Synchronises; not capturable. The request buffers must stay valid until
+ * rc_batch_destroy; their contents may change between runs.
+ * Errors: RC_EINVAL, RC_ENOMEM, RC_EHIP.
+ */
+rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_batch** out);
+
+/* Enqueues one run of the whole batch (LUT build, then correction) on
+ * `stream`; no synchronisation, no allocation. Runs on one batch must not
+ * overlap in time (they share the tile counters): order them on one stream.
+ * RC_EINVAL if the current device is not the batch's. */
+rc_status rc_batch_run(rc_batch* b, hipStream_t stream);
+
+rc_status rc_batch_info(const rc_batch* b, rc_batch_stats* stats);
+
+/* Frees the batch (its runs must have completed). NULL is ignored. */
+void rc_batch_destroy(rc_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

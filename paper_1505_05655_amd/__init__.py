@@ -60,6 +60,25 @@ class Plan(ctypes.Structure):
         return f"Plan({self.as_dict()})"
 
 
+class Request(ctypes.Structure):
+    """One job of a batch (mirrors rc_request); pointers are device addresses."""
+    _fields_ = [("coeffs", ctypes.c_void_p), ("dn", ctypes.c_void_p), ("lut", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("lines", ctypes.c_int64), ("detectors", ctypes.c_int32),
+                ("bands", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("pixels", ctypes.c_int64), ("lut_entries", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+RC_BATCH_NO_GRAPH = 1
+
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 _lib.rc_status_str.argtypes = [ctypes.c_int]
 _lib.rc_status_str.restype = ctypes.c_char_p
@@ -85,6 +104,14 @@ _lib.rc_tune_clear.argtypes = []
 _lib.rc_tune_clear.restype = None
 _lib.rc_tune_count.argtypes = []
 _lib.rc_tune_count.restype = _i32
+_lib.rc_batch_create.argtypes = [ctypes.POINTER(Request), _i32, _i32, ctypes.POINTER(_vp)]
+_lib.rc_batch_create.restype = ctypes.c_int
+_lib.rc_batch_run.argtypes = [_vp, _vp]
+_lib.rc_batch_run.restype = ctypes.c_int
+_lib.rc_batch_info.argtypes = [_vp, ctypes.POINTER(BatchStats)]
+_lib.rc_batch_info.restype = ctypes.c_int
+_lib.rc_batch_destroy.argtypes = [_vp]
+_lib.rc_batch_destroy.restype = None
 
 
 def lib():
@@ -171,6 +198,60 @@ def rc_tune_clear():
 
 def rc_tune_count():
     return _lib.rc_tune_count()
+
+
+def rc_batch_create(reqs, flags=0):
+    """reqs: sequence of Request. Returns an opaque handle (int)."""
+    arr = (Request * len(reqs))(*reqs)
+    h = _vp()
+    _check(_lib.rc_batch_create(arr, len(reqs), flags, ctypes.byref(h)), "rc_batch_create")
+    return h.value
+
+
+def rc_batch_run(handle, stream=None):
+    _check(_lib.rc_batch_run(handle, _stream(stream)), "rc_batch_run")
+
+
+def rc_batch_info(handle):
+    st = BatchStats()
+    _check(_lib.rc_batch_info(handle, ctypes.byref(st)), "rc_batch_info")
+    return st.as_dict()
+
+
+def rc_batch_destroy(handle):
+    _lib.rc_batch_destroy(handle)
+
+
+class Batch:
+    """Owns an rc_batch over device tensors: jobs = [(coeffs, dn, lut, out)], each
+    coeffs [B, D, 4] float64, dn/out [B, N, D] 16-bit, lut [B, D, L] 16-bit."""
+
+    def __init__(self, jobs, graph=True):
+        self.jobs = list(jobs)  # keeps the tensors alive
+        reqs = []
+        for c, dn, lut, out in self.jobs:
+            B, N, D = dn.shape
+            assert tuple(c.shape) == (B, D, 4) and tuple(lut.shape[:2]) == (B, D)
+            assert tuple(out.shape) == (B, N, D)
+            reqs.append(Request(_ptr(c), _ptr(dn), _ptr(lut), _ptr(out), N, D, B, lut.shape[2], 0))
+        self.handle = rc_batch_create(reqs, 0 if graph else RC_BATCH_NO_GRAPH)
+
+    def run(self, stream=None):
+        rc_batch_run(self.handle, stream)
+
+    def info(self):
+        return rc_batch_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            rc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # --- shape-checked conveniences -------------------------------------------------------------

@@ -106,19 +106,27 @@ int plan_slots(const rc_plan& plan, size_t lds_bytes, const DeviceInfo& di) {
     return std::max(1, per_cu) * std::max(1, di.cus);
 }
 
+int64_t max_chunk_lines(int32_t detectors, int32_t threads, int32_t unroll) {
+    // Tile pixels are addressed with 32-bit buffer offsets: a tile's lines
+    // plus up to two passes of overshoot must stay below 2^31 bytes.
+    return ((int64_t)1 << 31) / (2 * (int64_t)std::max(detectors, 1)) -
+           2 * (int64_t)threads * unroll;
+}
+
 size_t plan_lds_bytes(int path, int strip, int levels) {
     if (path == RC_PATH_LDS) return (size_t)strip * (size_t)levels * 2;
     if (path == RC_PATH_PACKED) return packed_lds_bytes(strip, levels);
     return 0;
 }
 
-// Default launch shape (no tuning). Strips are made as wide as an 80 KiB LDS
-// tile allows (two workgroups per CU), because measured HBM throughput of a
-// strip-shaped stream grows with the strip width: packed LDS rows for
-// L >= 512 (W = 256 at L = 1024, W = 64 at L = 4096), raw 16-bit rows for
-// smaller L, and the L2 path when fewer than 16 detectors would fit. Four
-// pixels per lane when alignment allows. The line chunk balances the tail of
-// the last wave of tiles against re-staging the LUT strip per tile.
+// Default launch shape (no tuning), from measurements on MI355X. Strips are
+// made as wide as an 80 KiB LDS tile allows (two workgroups per CU), because
+// the HBM throughput of strip-shaped streams grows with the strip width:
+// packed LDS rows for L >= 512 (W = 256 at L = 1024, W = 64 at L = 4096),
+// raw 16-bit rows for smaller L, and the L2 path when fewer than 16
+// detectors would fit. Lines are split into chunks (see below) unless
+// re-staging the LUT strip per chunk would add more than a fifth to the
+// image traffic.
 void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
                   const DeviceInfo& di, rc_plan* plan) {
     rc_plan p;
@@ -129,43 +137,43 @@ void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t level
     while (W > 1 && plan_lds_bytes(path_lds, W, levels) > budget) W >>= 1;
     const int64_t dcap = std::max<int64_t>(1, (int64_t)1 << (ilog2(detectors) +
                                                               (is_pow2(detectors) ? 0 : 1)));
-    p.vec = vmax >= 4 ? 4 : vmax;
     if (W >= 16) {
         p.path = path_lds;
-        p.strip = (int)std::max<int64_t>(p.vec, std::min<int64_t>(W, dcap));
+        p.strip = (int)std::min<int64_t>(W, dcap);
     } else {
         p.path = RC_PATH_L2;
-        p.strip = (int)std::max<int64_t>(p.vec, std::min<int64_t>(64, dcap));
+        p.strip = (int)std::min<int64_t>(64, dcap);
     }
-    p.threads = 256;
-    while (p.strip / p.vec > p.threads) p.threads *= 2;
-    p.unroll = p.vec == 4 ? 4 : 8;
+    p.vec = std::min(vmax, p.strip >= 128 ? 4 : 2);
+    while (p.vec > p.strip) p.vec >>= 1;
+    p.threads = 512;
+    p.unroll = 8;
     p.xcd_remap = 1;
-    p.nontemporal = 0;
+    p.nontemporal = p.strip >= 256 ? 1 : 0;
 
     const size_t lds_bytes = plan_lds_bytes(p.path, p.strip, levels);
     const int slots = plan_slots(p, lds_bytes, di);
     const int64_t strips = (detectors + p.strip - 1) / p.strip;
-    const int64_t base = (int64_t)bands * strips;
-    int64_t best_k = 1;
-    double best = -1.0;
-    const int64_t kmax = std::max<int64_t>(1, std::min<int64_t>(64, lines / 16));
-    for (int64_t k = 1; k <= kmax; ++k) {
-        const int64_t ch = (lines + k - 1) / k;
-        const int64_t chunks = (lines + ch - 1) / ch;
-        const int64_t tiles = base * chunks;
-        if (tiles > (int64_t)1 << 22) break;
-        const double waves = (double)tiles / slots;
-        const double eff = waves / std::ceil(waves);
-        const double stage = p.path != RC_PATH_L2 ? (double)levels * 2.0 / ((double)ch * 4.0) : 0;
-        double score = eff / (1.0 + stage);
-        if (p.path == RC_PATH_L2 && chunks < 32 && lines >= 32 * 64) score *= 0.5;
-        if (score > best * 1.0001) {
-            best = score;
-            best_k = k;
-        }
+    const int64_t base = std::max<int64_t>(1, (int64_t)bands * strips);
+    const int64_t cap = std::max<int64_t>(1, max_chunk_lines(detectors, p.threads, p.unroll));
+    const int64_t kmin = (lines + cap - 1) / cap;
+    // Wide strips stream fast enough per workgroup that one tile per strip is
+    // best once most CUs get one; narrower strips need about two waves of
+    // resident tiles to keep enough lines in flight.
+    int64_t k = (p.strip >= 256 && base * 10 >= (int64_t)di.cus * 6)
+                    ? 1
+                    : (2 * (int64_t)slots + base - 1) / base;
+    k = std::max(k, kmin);
+    if (p.path == RC_PATH_L2) {
+        k = std::max<int64_t>(k, 32);
+    } else {
+        // Re-staging cost of k chunks relative to the image bytes.
+        const int64_t kcap = std::max<int64_t>(1, (int64_t)(0.2 * 2.0 * (double)lines /
+                                                            (double)levels));
+        k = std::max<int64_t>(kmin, std::min(k, kcap));
     }
-    p.chunk_lines = (int32_t)std::min<int64_t>((lines + best_k - 1) / best_k, INT32_MAX);
+    k = std::min<int64_t>(k, std::max<int64_t>(1, lines));
+    p.chunk_lines = (int32_t)std::min<int64_t>((lines + k - 1) / k, INT32_MAX);
     *plan = p;
 }
 
@@ -183,6 +191,7 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
     if (plan.strip / plan.vec > plan.threads) return RC_EINVAL;
     const size_t bytes = plan_lds_bytes(plan.path, plan.strip, levels);
     if (bytes > di.lds) return RC_EINVAL;
+    if (plan.chunk_lines > max_chunk_lines(detectors, plan.threads, plan.unroll)) return RC_EINVAL;
     const int64_t strips = (detectors + (int64_t)plan.strip - 1) / plan.strip;
     const int64_t chunks = (lines + plan.chunk_lines - 1) / plan.chunk_lines;
     int64_t tiles = 0;

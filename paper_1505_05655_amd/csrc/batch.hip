@@ -1,0 +1,442 @@
+// Batched execution of many uneven correction requests (§I's LUT generation
+// and image correction, run for a whole queue of client scenes at once).
+//
+// Two kernels per run, captured once into a hipGraph and replayed:
+//  1. k_lut_build_batch: the LUT entries of the requests that are corrected
+//     from the global LUT (the L2 path, for level counts whose strips do not
+//     fit LDS); a thread finds its request by binary search over the prefix
+//     of work items.
+//  2. k_apply_batch: a persistent kernel (one workgroup per resident slot)
+//     whose workgroups pop tiles (request, band, strip, lines) from an atomic
+//     counter. For every other request a tile is fused: it evaluates its
+//     strip's LUT rows from the coefficients straight into LDS (the first
+//     line chunk of a strip also writes them to the request's LUT), then
+//     corrects its lines, so the LUT is never read back from memory and the
+//     binary64 evaluation of one workgroup overlaps the streaming of others.
+//     Tiles are sorted longest first, so the tail of the batch is made of
+//     short tiles. The last workgroup to finish resets the counters, so a
+//     replay needs no memset node.
+// Strip width, LDS mode and pixels per lane per request come from the plan
+// the plain path would use for that request (tuned if the plan cache has
+// one), forced to the batch kernel's fixed workgroup size.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "device_ops.h"
+#include "kernels.h"
+#include "rc.h"
+#include "runtime.h"
+
+namespace rc {
+
+// Per-request descriptor, resident in device memory.
+struct BatchReq {
+    const double* coeffs;
+    const uint16_t* dn;
+    uint16_t* lut;
+    uint16_t* out;
+    int64_t lines;
+    int32_t detectors;
+    int32_t bands;
+    int32_t levels;
+    int32_t log_strip;
+    int32_t vec;
+    int32_t mode;     // kRaw / kGlobal / kPacked
+    int32_t lut_vec;  // LUT rows allow 16-byte loads/stores
+    int32_t fused;    // tiles build their LUT strip in LDS (mode kRaw / kPacked)
+};
+
+struct BatchTile {
+    int32_t req;
+    int32_t band;
+    int32_t d0;
+    int32_t pad;
+    int64_t n0;
+    int64_t n1;
+};
+
+constexpr int kBatchThreads = 1024;
+constexpr int kBatchUnroll = 4;
+constexpr size_t kBatchLds = 80 * 1024;
+
+__global__ __launch_bounds__(256) void k_lut_build_batch(const BatchReq* __restrict__ reqs,
+                                                         const int64_t* __restrict__ prefix,
+                                                         int32_t nreq, int64_t total) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        // Request r owns work items [prefix[r], prefix[r + 1]).
+        int lo = 0, hi = nreq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchReq& q = reqs[lo];
+        const int L = q.levels;
+        const int chunks = (L + 7) >> 3;
+        const int64_t local = t - prefix[lo];
+        const int64_t row = local / chunks;
+        const int c = (int)(local - row * chunks);
+        const double* a = q.coeffs + row * 4;
+        const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
+        const double lim = (double)L;
+        const int v0 = c * 8;
+        uint16_t* dst = q.lut + row * (int64_t)L + v0;
+        if (q.lut_vec) {
+            uint32_t e[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[k] = lut_entry(a0, a1, a2, a3, v0 + k, lim);
+            u32x4 w;
+            w.x = e[0] | (e[1] << 16);
+            w.y = e[2] | (e[3] << 16);
+            w.z = e[4] | (e[5] << 16);
+            w.w = e[6] | (e[7] << 16);
+            *(u32x4*)dst = w;
+        } else {
+            for (int k = 0; k < 8 && v0 + k < L; ++k) {
+                dst[k] = (uint16_t)lut_entry(a0, a1, a2, a3, v0 + k, lim);
+            }
+        }
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ void batch_tile_vec(const BatchReq& q, const BatchTile& tl,
+                                               void* smem) {
+    const int W = 1 << q.log_strip;
+    const int weff = min(W, q.detectors - tl.d0);
+    if (q.fused) {
+        const bool write_lut = tl.n0 == 0;
+        if (q.mode == kPacked) {
+            fused_tile<VEC, kBatchUnroll, kPacked>(q.coeffs, q.dn, q.lut, q.out, q.lines,
+                                                   q.detectors, q.levels, q.log_strip, tl.band,
+                                                   tl.d0, weff, tl.n0, tl.n1, write_lut, smem,
+                                                   q.lut_vec != 0);
+        } else {
+            fused_tile<VEC, kBatchUnroll, kRaw>(q.coeffs, q.dn, q.lut, q.out, q.lines,
+                                                q.detectors, q.levels, q.log_strip, tl.band,
+                                                tl.d0, weff, tl.n0, tl.n1, write_lut, smem,
+                                                q.lut_vec != 0);
+        }
+    } else {
+        apply_tile<VEC, kBatchUnroll, false, kGlobal>(q.dn, q.lut, q.out, q.lines, q.detectors,
+                                                      q.levels, q.log_strip, tl.band, tl.d0,
+                                                      weff, tl.n0, tl.n1, smem, q.lut_vec != 0);
+    }
+}
+
+// counters[0]: next tile; counters[1]: workgroups finished.
+__global__ __launch_bounds__(kBatchThreads) void k_apply_batch(const BatchReq* __restrict__ reqs,
+                                                               const BatchTile* __restrict__ tiles,
+                                                               int32_t ntiles,
+                                                               unsigned int* counters) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&counters[0], 1u);
+        __syncthreads();
+        // Uniform across the workgroup: descriptor loads become scalar loads.
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (t >= ntiles) break;
+        const BatchTile tl = tiles[t];
+        const BatchReq q = reqs[tl.req];
+        if (q.vec == 4) batch_tile_vec<4>(q, tl, smem);
+        else if (q.vec == 2) batch_tile_vec<2>(q, tl, smem);
+        else batch_tile_vec<1>(q, tl, smem);
+    }
+    if (threadIdx.x == 0) {
+        const unsigned int done = atomicAdd(&counters[1], 1u);
+        if (done == gridDim.x - 1) {
+            // Every workgroup has made its last pop: rearm for the next run.
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+        }
+    }
+}
+
+}  // namespace rc
+
+using namespace rc;
+
+struct rc_batch {
+    int device = 0;
+    int32_t nreq = 0;
+    int32_t ntiles = 0;
+    int64_t build_items = 0;
+    int slots = 0;
+    size_t lds = 0;
+    BatchReq* d_reqs = nullptr;
+    BatchTile* d_tiles = nullptr;
+    int64_t* d_prefix = nullptr;
+    unsigned int* d_counters = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = true;
+    rc_batch_stats stats{};
+};
+
+namespace {
+
+void release(rc_batch* b) {
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->cap) hipStreamDestroy(b->cap);
+    if (b->d_reqs) hipFree(b->d_reqs);
+    if (b->d_tiles) hipFree(b->d_tiles);
+    if (b->d_prefix) hipFree(b->d_prefix);
+    if (b->d_counters) hipFree(b->d_counters);
+    delete b;
+}
+
+struct Range {
+    uintptr_t lo, hi;
+    int req;
+    bool written;
+};
+
+// A buffer written by one request may not overlap any buffer (read or
+// written) of another request, nor may two written buffers overlap.
+bool hazards(const std::vector<Range>& rs) {
+    for (size_t a = 0; a < rs.size(); ++a) {
+        if (!rs[a].written) continue;
+        for (size_t b = 0; b < rs.size(); ++b) {
+            if (a == b) continue;
+            if (rs[b].req == rs[a].req && !rs[b].written) continue;  // own inputs (in place)
+            if (rs[a].lo < rs[b].hi && rs[b].lo < rs[a].hi) return true;
+        }
+    }
+    return false;
+}
+
+hipError_t enqueue(const rc_batch* b, hipStream_t s) {
+    if (b->build_items > 0) {
+        int64_t blocks = (b->build_items + 255) / 256;
+        if (blocks > ((int64_t)1 << 20)) blocks = (int64_t)1 << 20;
+        hipLaunchKernelGGL(k_lut_build_batch, dim3((unsigned)blocks), dim3(256), 0, s, b->d_reqs,
+                           b->d_prefix, b->nreq, b->build_items);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (b->ntiles > 0) {
+        hipLaunchKernelGGL(k_apply_batch, dim3((unsigned)b->slots), dim3(kBatchThreads), b->lds, s,
+                           b->d_reqs, b->d_tiles, b->ntiles, b->d_counters);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_batch** out) {
+    if (!out || n < 0 || (n > 0 && !reqs)) return RC_EINVAL;
+    *out = nullptr;
+    // Pass 1, host only: validate every request and the hazards between them.
+    std::vector<Range> ranges;
+    for (int32_t i = 0; i < n; ++i) {
+        const rc_request& r = reqs[i];
+        if (r.lines < 0 || r.detectors < 0 || r.bands < 0 || r.reserved != 0) return RC_EINVAL;
+        if (r.levels < RC_LEVELS_MIN || r.levels > RC_LEVELS_MAX) return RC_EINVAL;
+        int64_t px = 0, rows = 0, lut_n = 0;
+        if (!mul_ok(r.lines, r.detectors, &px) || !mul_ok(px, r.bands, &px) ||
+            !mul_ok((int64_t)r.bands, r.detectors, &rows) || !mul_ok(rows, r.levels, &lut_n) ||
+            px > INT64_MAX / 2 || lut_n > INT64_MAX / 2)
+            return RC_EINVAL;
+        if (rows > 0) {
+            if (!r.coeffs || !r.lut || ((uintptr_t)r.coeffs & 7u) || ((uintptr_t)r.lut & 1u))
+                return RC_EINVAL;
+            if (overlaps(r.coeffs, (size_t)rows * 32, r.lut, (size_t)lut_n * 2)) return RC_EINVAL;
+            ranges.push_back({(uintptr_t)r.lut, (uintptr_t)r.lut + (uintptr_t)lut_n * 2, i, true});
+            ranges.push_back({(uintptr_t)r.coeffs, (uintptr_t)r.coeffs + (uintptr_t)rows * 32, i,
+                              false});
+        }
+        if (px > 0) {
+            if (!r.dn || !r.out || (((uintptr_t)r.dn | (uintptr_t)r.out) & 1u)) return RC_EINVAL;
+            if (r.dn != r.out && overlaps(r.dn, (size_t)px * 2, r.out, (size_t)px * 2))
+                return RC_EINVAL;
+            // The LUT is written before the image is read: it may not overlap dn.
+            if (overlaps(r.lut, (size_t)lut_n * 2, r.dn, (size_t)px * 2)) return RC_EINVAL;
+            ranges.push_back({(uintptr_t)r.out, (uintptr_t)r.out + (uintptr_t)px * 2, i, true});
+            ranges.push_back({(uintptr_t)r.dn, (uintptr_t)r.dn + (uintptr_t)px * 2, i, false});
+        }
+    }
+    if (hazards(ranges)) return RC_EINVAL;
+
+    // Pass 2: per-request plans and the tile queue.
+    const DeviceInfo* di = current_device();
+    if (!di) return RC_EHIP;
+    const size_t lds_cap = std::min(kBatchLds, di->lds);
+    std::vector<BatchReq> hreq;
+    std::vector<BatchTile> htile;
+    std::vector<int64_t> prefix(1, 0);
+    int64_t total_px = 0, total_lut = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const rc_request& r = reqs[i];
+        const int64_t px = r.lines * r.detectors * (int64_t)r.bands;
+        const int64_t rows = (int64_t)r.bands * r.detectors;
+        const int64_t lut_n = rows * r.levels;
+        BatchReq q;
+        std::memset(&q, 0, sizeof q);
+        q.coeffs = r.coeffs;
+        q.dn = r.dn;
+        q.lut = r.lut;
+        q.out = r.out;
+        q.lines = r.lines;
+        q.detectors = r.detectors;
+        q.bands = r.bands;
+        q.levels = r.levels;
+        q.lut_vec = (r.levels % 8 == 0 && ((uintptr_t)r.lut & 15u) == 0) ? 1 : 0;
+        if (rows > 0) {
+            const int vmax = px > 0 ? max_vec(r.dn, r.out, r.detectors) : 1;
+            const int64_t lines_p = std::max<int64_t>(r.lines, 1);
+            rc_plan p;
+            if (!tuned_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p))
+                default_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p);
+            // Fit the plan to the batch kernel: fixed workgroup size, LDS budget.
+            while (p.path != RC_PATH_L2 && plan_lds_bytes(p.path, p.strip, r.levels) > lds_cap &&
+                   p.strip > p.vec)
+                p.strip >>= 1;
+            if (p.path != RC_PATH_L2 && plan_lds_bytes(p.path, p.strip, r.levels) > lds_cap)
+                p.path = RC_PATH_L2;
+            if (p.strip / p.vec > kBatchThreads) p.strip = kBatchThreads * p.vec;
+            int lw = 0;
+            while ((1 << (lw + 1)) <= p.strip) ++lw;
+            q.log_strip = lw;
+            q.vec = p.vec;
+            q.mode = p.path == RC_PATH_LDS ? kRaw : (p.path == RC_PATH_PACKED ? kPacked : kGlobal);
+            q.fused = q.mode == kGlobal ? 0 : 1;
+            // One tile per (band, strip) and line chunk; strips of up to 8192
+            // lines are not split (re-staging the LUT strip per chunk would
+            // re-read it), longer ones are cut into chunks of at most 8192.
+            const int W = 1 << lw;
+            const int64_t cap = std::min<int64_t>(
+                8192, max_chunk_lines(r.detectors, kBatchThreads, kBatchUnroll));
+            if (cap < 1) return RC_EINVAL;  // lines too wide for 32-bit tile offsets
+            const int64_t ch = std::max<int64_t>(1, std::min<int64_t>(r.lines, cap));
+            for (int32_t b = 0; b < r.bands; ++b)
+                for (int32_t d0 = 0; d0 < r.detectors; d0 += W) {
+                    // A fused request with no lines still gets one tile per
+                    // strip, which only builds the LUT.
+                    const int64_t nend = (r.lines == 0 && q.fused) ? 1 : r.lines;
+                    for (int64_t n0 = 0; n0 < nend; n0 += ch) {
+                        BatchTile tl;
+                        tl.req = i;
+                        tl.band = b;
+                        tl.d0 = d0;
+                        tl.pad = 0;
+                        tl.n0 = n0;
+                        tl.n1 = std::min(r.lines, n0 + ch);
+                        htile.push_back(tl);
+                    }
+                }
+        }
+        hreq.push_back(q);
+        const int64_t items = q.fused ? 0 : rows * (int64_t)((r.levels + 7) / 8);
+        prefix.push_back(prefix.back() + items);
+        total_px += px;
+        total_lut += lut_n;
+    }
+    if (htile.size() > (size_t)INT32_MAX) return RC_EINVAL;
+    // Longest tiles first: image bytes of the tile plus its LUT strip (a
+    // fused tile's binary64 evaluation counted like 6 bytes per entry).
+    auto cost = [&](const BatchTile& t) {
+        const BatchReq& q = hreq[t.req];
+        const int64_t w = std::min<int64_t>(1 << q.log_strip, q.detectors - t.d0);
+        return w * ((t.n1 - t.n0) * 4 + (int64_t)q.levels * (q.fused ? 6 : 2));
+    };
+    std::stable_sort(htile.begin(), htile.end(),
+                     [&](const BatchTile& a, const BatchTile& b) { return cost(a) > cost(b); });
+
+    rc_batch* bt = new (std::nothrow) rc_batch();
+    if (!bt) return RC_ENOMEM;
+    hipGetDevice(&bt->device);
+    bt->nreq = n;
+    bt->ntiles = (int32_t)htile.size();
+    bt->build_items = prefix.back();
+    bt->lds = lds_cap;
+    bt->use_graph = !(flags & RC_BATCH_NO_GRAPH);
+    bt->slots = std::max(1, di->cus) * (int)std::max<size_t>(1, std::min<size_t>(
+                                                                    2, di->lds_per_cu / lds_cap));
+    hipError_t e = hipSuccess;
+    auto fail = [&](hipError_t err) {
+        release(bt);
+        return err == hipErrorOutOfMemory ? RC_ENOMEM : hip_fail(err);
+    };
+    if (n > 0) {
+        if ((e = hipMalloc(&bt->d_reqs, sizeof(BatchReq) * n)) != hipSuccess) return fail(e);
+        if ((e = hipMalloc(&bt->d_prefix, sizeof(int64_t) * (n + 1))) != hipSuccess) return fail(e);
+    }
+    if (!htile.empty() &&
+        (e = hipMalloc(&bt->d_tiles, sizeof(BatchTile) * htile.size())) != hipSuccess)
+        return fail(e);
+    if ((e = hipMalloc(&bt->d_counters, 2 * sizeof(unsigned int))) != hipSuccess) return fail(e);
+    if ((e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking)) != hipSuccess)
+        return fail(e);
+    if (n > 0) {
+        if ((e = hipMemcpyAsync(bt->d_reqs, hreq.data(), sizeof(BatchReq) * n,
+                                hipMemcpyHostToDevice, bt->cap)) != hipSuccess)
+            return fail(e);
+        if ((e = hipMemcpyAsync(bt->d_prefix, prefix.data(), sizeof(int64_t) * (n + 1),
+                                hipMemcpyHostToDevice, bt->cap)) != hipSuccess)
+            return fail(e);
+    }
+    if (!htile.empty() &&
+        (e = hipMemcpyAsync(bt->d_tiles, htile.data(), sizeof(BatchTile) * htile.size(),
+                            hipMemcpyHostToDevice, bt->cap)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemsetAsync(bt->d_counters, 0, 2 * sizeof(unsigned int), bt->cap)) != hipSuccess)
+        return fail(e);
+    if ((e = hipStreamSynchronize(bt->cap)) != hipSuccess) return fail(e);
+    if ((e = hipFuncSetAttribute((const void*)k_apply_batch,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap)) !=
+        hipSuccess)
+        return fail(e);
+    if (bt->use_graph) {
+        if ((e = hipStreamBeginCapture(bt->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return fail(e);
+        const hipError_t le = enqueue(bt, bt->cap);
+        e = hipStreamEndCapture(bt->cap, &bt->graph);
+        if (le != hipSuccess) return fail(le);
+        if (e != hipSuccess) return fail(e);
+        if ((e = hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0)) != hipSuccess)
+            return fail(e);
+    }
+    rc_batch_stats& st = bt->stats;
+    st.requests = n;
+    st.tiles = bt->ntiles;
+    st.slots = bt->slots;
+    st.pixels = total_px;
+    st.lut_entries = total_lut;
+    st.graph = bt->use_graph ? 1 : 0;
+    *out = bt;
+    return RC_OK;
+}
+
+rc_status rc_batch_run(rc_batch* b, hipStream_t stream) {
+    if (!b) return RC_EINVAL;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev != b->device) return RC_EINVAL;
+    e = b->use_graph ? hipGraphLaunch(b->exec, stream) : enqueue(b, stream);
+    return e == hipSuccess ? RC_OK : hip_fail(e);
+}
+
+rc_status rc_batch_info(const rc_batch* b, rc_batch_stats* st) {
+    if (!b || !st) return RC_EINVAL;
+    *st = b->stats;
+    return RC_OK;
+}
+
+void rc_batch_destroy(rc_batch* b) { release(b); }
+
+}  // extern "C"

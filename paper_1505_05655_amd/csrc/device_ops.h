@@ -18,10 +18,16 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // LUT entry for integer level v (§I LUT generation, definition in rc.h):
-// Horner from the cubic coefficient down, then C round() (halfway away from
-// zero, exact), then the clamp to [0, top] done in binary64 before converting.
+// Horner from the cubic coefficient down, one rounding per operation, then
+// round half away from zero and clamp to [0, L-1]. `lim` is (double)L.
+// The rounding and clamp are done as: c = min(max(acc, 0), L) in binary64
+// (maxNum sends NaN to 0, -Inf and every negative to 0, +Inf to L), then
+// i = trunc(c) and r = i + (c - i >= 0.5), then min(r, L-1). For c in
+// [0, L] the difference c - i is exact, so r equals round-half-away(acc)
+// whenever 0 <= acc <= L, and the integer clamp gives the defined value at
+// both ends.
 __device__ __forceinline__ uint32_t lut_entry(double a0, double a1, double a2, double a3, int v,
-                                              double top) {
+                                              double lim) {
     const double x = (double)v;
     double acc = a3;
     acc = acc * x;
@@ -30,10 +36,11 @@ __device__ __forceinline__ uint32_t lut_entry(double a0, double a1, double a2, d
     acc = acc + a1;
     acc = acc * x;
     acc = acc + a0;
-    const double r = __builtin_round(acc);
-    if (!(r > 0.0)) return 0u;  // negatives, -0, NaN
-    if (r >= top) return (uint32_t)top;
-    return (uint32_t)r;
+    const double c = __builtin_fmin(__builtin_fmax(acc, 0.0), lim);
+    const uint32_t i = (uint32_t)c;
+    const uint32_t r = i + ((c - (double)i) >= 0.5 ? 1u : 0u);
+    const uint32_t top = (uint32_t)lim - 1u;
+    return r < top ? r : top;
 }
 
 // Workgroups are dispatched round-robin over the XCDs (block i runs on XCD
@@ -44,18 +51,6 @@ __device__ __forceinline__ int xcd_tile(int i, int G, int X) {
     const int q = G / X, r = G - (G / X) * X;
     const int x = i % X, k = i / X;
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
-}
-
-template <typename T, bool NTH>
-__device__ __forceinline__ T load_px(const T* p) {
-    if constexpr (NTH) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-
-template <typename T, bool NTH>
-__device__ __forceinline__ void store_px(T* p, T v) {
-    if constexpr (NTH) __builtin_nontemporal_store(v, p);
-    else *p = v;
 }
 
 // VEC pixels of one line held by one lane.
@@ -81,29 +76,72 @@ __device__ __forceinline__ typename Px<VEC>::T map_px(typename Px<VEC>::T w, F f
     }
 }
 
-// Streams lines [n0, n1) of detectors [col, col + VEC) of band `band0 / N`:
-// UNROLL lines (rpp apart) are loaded before any is gathered and stored, so
-// many loads are in flight per lane.
+// Raw buffer resource over `bytes` bytes from `base` (gfx9-family word 3:
+// untyped 32-bit data). Buffer loads past `bytes` return 0 and stores past
+// it are dropped, so a tile's last partial pass needs no per-line guard.
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             kRsrcWord3);
+}
+
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+// VEC pixels of one line through a buffer resource: per-lane byte offset
+// `vo` (VGPR) plus a wave-uniform line offset `so` (SGPR). NTH sets the
+// non-temporal cache policy.
+template <int VEC, bool NTH> struct Buf;
+template <bool NTH> struct Buf<1, NTH> {
+    static __device__ __forceinline__ unsigned short ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
+                                                        uint32_t so) {
+        return (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so,
+                                                                    NTH ? 2 : 0);
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                              unsigned short v) {
+        __builtin_amdgcn_raw_buffer_store_b16((short)v, r, (int)vo, (int)so, NTH ? 2 : 0);
+    }
+};
+template <bool NTH> struct Buf<2, NTH> {
+    static __device__ __forceinline__ unsigned int ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
+                                                      uint32_t so) {
+        return (unsigned int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so,
+                                                                  NTH ? 2 : 0);
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                              unsigned int v) {
+        __builtin_amdgcn_raw_buffer_store_b32((int)v, r, (int)vo, (int)so, NTH ? 2 : 0);
+    }
+};
+template <bool NTH> struct Buf<4, NTH> {
+    static __device__ __forceinline__ u32x2 ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
+                                               uint32_t so) {
+        return (u32x2)__builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, NTH ? 2 : 0);
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                              u32x2 v) {
+        __builtin_amdgcn_raw_buffer_store_b64((i32x2)v, r, (int)vo, (int)so, NTH ? 2 : 0);
+    }
+};
+
+// Streams `passes` passes over a tile's lines: in each pass a lane loads its
+// VEC pixels from UNROLL lines (line_stride bytes apart) before it gathers
+// and stores any of them, so many loads are in flight per lane.
 template <int VEC, int UNROLL, bool NTH, typename G>
-__device__ __forceinline__ void stream_lines(const uint16_t* dn, uint16_t* out, size_t Dz,
-                                             size_t band0, size_t col, int64_t first, int64_t n1,
-                                             int rpp, G gather) {
+__device__ __forceinline__ void stream_lines(__amdgpu_buffer_rsrc_t rin,
+                                             __amdgpu_buffer_rsrc_t rout, uint32_t vo,
+                                             uint32_t line_stride, int passes, G gather) {
     typedef typename Px<VEC>::T T;
-    for (int64_t n = first; n < n1; n += (int64_t)rpp * UNROLL) {
+    uint32_t so = 0;
+    for (int k = 0; k < passes; ++k) {
         T w[UNROLL];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            const int64_t nn = n + (int64_t)u * rpp;
-            if (nn < n1) w[u] = load_px<T, NTH>((const T*)(dn + (band0 + (size_t)nn) * Dz + col));
-        }
+        for (int u = 0; u < UNROLL; ++u) w[u] = Buf<VEC, NTH>::ld(rin, vo, so + u * line_stride);
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            const int64_t nn = n + (int64_t)u * rpp;
-            if (nn < n1) {
-                store_px<T, NTH>((T*)(out + (band0 + (size_t)nn) * Dz + col),
-                                 map_px<VEC>(w[u], gather));
-            }
-        }
+        for (int u = 0; u < UNROLL; ++u)
+            Buf<VEC, NTH>::st(rout, vo, so + u * line_stride, map_px<VEC>(w[u], gather));
+        so += UNROLL * line_stride;
     }
 }
 
@@ -175,30 +213,51 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
     const int lane = tid & ((1 << logq) - 1);
     const int rpp = nt >> logq;      // lines per pass
     const int j = lane * VEC;
-    const size_t band0 = (size_t)b * (size_t)N;
-    const size_t col = (size_t)d0 + (size_t)j;
-    const int64_t first = n0 + (tid >> logq);
+    // The tile's image bytes as buffer resources: line n0, detector d0 is at
+    // byte 0; the range ends after the tile's last pixel.
+    const size_t tile0 = ((size_t)b * (size_t)N + (size_t)n0) * (size_t)D + (size_t)d0;
+    const uint32_t span = (uint32_t)((((size_t)(n1 - n0) - 1) * (size_t)D + (size_t)weff) * 2);
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(dn + tile0, span);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + tile0, span);
+    const uint32_t vo = (uint32_t)(((size_t)(tid >> logq) * (size_t)D + (size_t)j) * 2);
+    const uint32_t line_stride = (uint32_t)rpp * (uint32_t)D * 2u;
+    const int passes = (int)((n1 - n0 + (int64_t)rpp * UNROLL - 1) / ((int64_t)rpp * UNROLL));
 
     if constexpr (MODE == kRaw) {
         uint16_t* tile = (uint16_t*)smem;
         // Stage: lanes run along detectors (j fastest) so that one wave's
         // 16-bit LDS writes land in consecutive addresses.
         if (lut_vec) {
+            // Rounds of SU items per thread, loads first (latency overlap).
+            constexpr int SU = 8;
             const int items = (L >> 3) << logW;
-            for (int it = tid; it < items; it += nt) {
-                const int jj = it & (W - 1);
-                const int vc = it >> logW;
-                if (jj < weff) {
-                    const u32x4 q = *(const u32x4*)(strip_lut + (size_t)jj * Lz + vc * 8);
-                    uint16_t* dst = tile + ((vc * 8) << logW) + jj;
-                    dst[0] = (uint16_t)(q.x & 0xffffu);
-                    dst[1 << logW] = (uint16_t)(q.x >> 16);
-                    dst[2 << logW] = (uint16_t)(q.y & 0xffffu);
-                    dst[3 << logW] = (uint16_t)(q.y >> 16);
-                    dst[4 << logW] = (uint16_t)(q.z & 0xffffu);
-                    dst[5 << logW] = (uint16_t)(q.z >> 16);
-                    dst[6 << logW] = (uint16_t)(q.w & 0xffffu);
-                    dst[7 << logW] = (uint16_t)(q.w >> 16);
+            for (int it0 = tid; it0 < items; it0 += nt * SU) {
+                u32x4 qv[SU];
+#pragma unroll
+                for (int s = 0; s < SU; ++s) {
+                    const int it = it0 + s * nt;
+                    const int jj = it & (W - 1);
+                    qv[s] = u32x4{0u, 0u, 0u, 0u};
+                    if (it < items && jj < weff) {
+                        qv[s] = *(const u32x4*)(strip_lut + (size_t)jj * Lz + (it >> logW) * 8);
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < SU; ++s) {
+                    const int it = it0 + s * nt;
+                    const int jj = it & (W - 1);
+                    if (it < items && jj < weff) {
+                        const u32x4 q = qv[s];
+                        uint16_t* dst = tile + (((it >> logW) * 8) << logW) + jj;
+                        dst[0] = (uint16_t)(q.x & 0xffffu);
+                        dst[1 << logW] = (uint16_t)(q.x >> 16);
+                        dst[2 << logW] = (uint16_t)(q.y & 0xffffu);
+                        dst[3 << logW] = (uint16_t)(q.y >> 16);
+                        dst[4 << logW] = (uint16_t)(q.z & 0xffffu);
+                        dst[5 << logW] = (uint16_t)(q.z >> 16);
+                        dst[6 << logW] = (uint16_t)(q.w & 0xffffu);
+                        dst[7 << logW] = (uint16_t)(q.w >> 16);
+                    }
                 }
             }
         } else {
@@ -212,7 +271,7 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
         __syncthreads();
         if (j < weff) {
             stream_lines<VEC, UNROLL, NTH>(
-                dn, out, (size_t)D, band0, col, first, n1, rpp,
+                rin, rout, vo, line_stride, passes,
                 [&](int k, uint32_t d) { return g_raw(tile, d, top, logW, j + k); });
         }
         __syncthreads();  // the tile may be restaged next
@@ -220,73 +279,337 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
         if (j < weff) {
             const uint16_t* lrow = strip_lut + (size_t)j * Lz;
             stream_lines<VEC, UNROLL, NTH>(
-                dn, out, (size_t)D, band0, col, first, n1, rpp,
+                rin, rout, vo, line_stride, passes,
                 [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
         }
     } else {
         const int NB = (L + 31) >> 5;
         u32x2* planes = (u32x2*)smem;
         uint16_t* bases = (uint16_t*)(planes + (size_t)NB * W);
-        // Stage: item = (detector jj, block) with blocks fastest, so a wave
-        // reads long contiguous runs of one LUT row.
         int bad = 0;
-        const int items = weff * NB;
-        for (int it = tid; it < items; it += nt) {
-            const int jj = it / NB;
-            const int blk = it - jj * NB;
-            const uint16_t* src = strip_lut + (size_t)jj * Lz + (size_t)blk * 32;
-            const int cnt = min(32, L - blk * 32);
-            uint32_t e[32];
-            if (lut_vec && cnt == 32) {
+        if (lut_vec && (L & 31) == 0 && logW >= 4) {
+            // Stage, coalesced and bank-conflict free: a wave packs 16
+            // consecutive LDS positions of one level block. Lane 4g+q loads
+            // the q-th 16-byte quarter (8 entries) of the block's row for
+            // position p0+g; the four quarters' steps are merged by lane
+            // shuffles and lane 4g writes the block's words.
+            const int wl = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+            const int g = wl >> 2, q = wl & 3;
+            const int logpg = logW - 4;
+            const int units = NB << logpg;
+            // Rounds of SU units per wave: all SU loads are issued before the
+            // first unit is packed, so staging is not one load latency per unit.
+            constexpr int SU = 8;
+            for (int u0 = wv; u0 < units; u0 += nwv * SU) {
+                u32x4 qv[SU];
 #pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const u32x4 q = *(const u32x4*)(src + q4 * 8);
-                    e[q4 * 8 + 0] = q.x & 0xffffu;
-                    e[q4 * 8 + 1] = q.x >> 16;
-                    e[q4 * 8 + 2] = q.y & 0xffffu;
-                    e[q4 * 8 + 3] = q.y >> 16;
-                    e[q4 * 8 + 4] = q.z & 0xffffu;
-                    e[q4 * 8 + 5] = q.z >> 16;
-                    e[q4 * 8 + 6] = q.w & 0xffffu;
-                    e[q4 * 8 + 7] = q.w >> 16;
+                for (int s = 0; s < SU; ++s) {
+                    const int u = u0 + s * nwv;
+                    const int p = ((u & ((1 << logpg) - 1)) << 4) + g;
+                    const int jj = ((p & ((1 << logq) - 1)) << LOGVEC) + (p >> logq);
+                    qv[s] = u32x4{0u, 0u, 0u, 0u};
+                    if (u < units && jj < weff) {
+                        qv[s] = *(const u32x4*)(strip_lut + (size_t)jj * Lz +
+                                                (size_t)(u >> logpg) * 32 + q * 8);
+                    }
                 }
-            } else {
 #pragma unroll
-                for (int i = 0; i < 32; ++i) e[i] = i < cnt ? src[i] : 0u;
-            }
-            uint32_t lo = 0, hi = 0;
+                for (int s = 0; s < SU; ++s) {
+                    const int u = u0 + s * nwv;
+                    if (u >= units) break;  // uniform across the wave
+                    const int blk = u >> logpg;
+                    const int p = ((u & ((1 << logpg) - 1)) << 4) + g;
+                    const int jj = ((p & ((1 << logq) - 1)) << LOGVEC) + (p >> logq);
+                    const bool valid = jj < weff;
+                    const u32x4 v4 = qv[s];
+                    const uint32_t e[8] = {v4.x & 0xffffu, v4.x >> 16, v4.y & 0xffffu,
+                                           v4.y >> 16,     v4.z & 0xffffu, v4.z >> 16,
+                                           v4.w & 0xffffu, v4.w >> 16};
+                    const uint32_t nxt = (uint32_t)__shfl_down((int)e[0], 1, 64);
+                    uint32_t lo8 = 0, hi8 = 0, over = 0;
 #pragma unroll
-            for (int i = 0; i < 31; ++i) {
-                if (i + 1 < cnt) {
-                    const uint32_t step = e[i + 1] - e[i];  // wraps when negative
-                    bad |= step > 3u;
-                    lo |= (step & 1u) << i;
-                    hi |= ((step >> 1) & 1u) << i;
+                    for (int i = 0; i < 8; ++i) {
+                        // Step from entry 8q+i to 8q+i+1; block step 31 does not exist.
+                        const uint32_t step =
+                            i < 7 ? e[i + 1] - e[i] : (q < 3 ? nxt - e[7] : 0u);
+                        over |= step > 3u;
+                        lo8 |= (step & 1u) << i;
+                        hi8 |= ((step >> 1) & 1u) << i;
+                    }
+                    uint32_t lo = lo8 << (q * 8), hi = hi8 << (q * 8);
+                    lo |= (uint32_t)__shfl_xor((int)lo, 1, 64);
+                    hi |= (uint32_t)__shfl_xor((int)hi, 1, 64);
+                    lo |= (uint32_t)__shfl_xor((int)lo, 2, 64);
+                    hi |= (uint32_t)__shfl_xor((int)hi, 2, 64);
+                    if (valid) {
+                        bad |= (int)over;
+                        if (q == 0) {
+                            u32x2 pl;
+                            pl.x = lo;
+                            pl.y = hi;
+                            planes[blk * W + p] = pl;
+                            bases[blk * W + p] = (uint16_t)e[0];
+                        }
+                    }
                 }
             }
-            const int p = ((jj & (VEC - 1)) << logq) + (jj >> LOGVEC);
-            u32x2 pl;
-            pl.x = lo;
-            pl.y = hi;
-            planes[blk * W + p] = pl;
-            bases[blk * W + p] = (uint16_t)e[0];
+        } else {
+            // Stage, general shapes: item = (detector jj, block), blocks fastest.
+            const int items = weff * NB;
+            for (int it = tid; it < items; it += nt) {
+                const int jj = it / NB;
+                const int blk = it - jj * NB;
+                const uint16_t* src = strip_lut + (size_t)jj * Lz + (size_t)blk * 32;
+                const int cnt = min(32, L - blk * 32);
+                uint32_t e[32];
+                if (lut_vec && cnt == 32) {
+    #pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        const u32x4 q = *(const u32x4*)(src + q4 * 8);
+                        e[q4 * 8 + 0] = q.x & 0xffffu;
+                        e[q4 * 8 + 1] = q.x >> 16;
+                        e[q4 * 8 + 2] = q.y & 0xffffu;
+                        e[q4 * 8 + 3] = q.y >> 16;
+                        e[q4 * 8 + 4] = q.z & 0xffffu;
+                        e[q4 * 8 + 5] = q.z >> 16;
+                        e[q4 * 8 + 6] = q.w & 0xffffu;
+                        e[q4 * 8 + 7] = q.w >> 16;
+                    }
+                } else {
+    #pragma unroll
+                    for (int i = 0; i < 32; ++i) e[i] = i < cnt ? src[i] : 0u;
+                }
+                uint32_t lo = 0, hi = 0;
+    #pragma unroll
+                for (int i = 0; i < 31; ++i) {
+                    if (i + 1 < cnt) {
+                        const uint32_t step = e[i + 1] - e[i];  // wraps when negative
+                        bad |= step > 3u;
+                        lo |= (step & 1u) << i;
+                        hi |= ((step >> 1) & 1u) << i;
+                    }
+                }
+                const int p = ((jj & (VEC - 1)) << logq) + (jj >> LOGVEC);
+                u32x2 pl;
+                pl.x = lo;
+                pl.y = hi;
+                planes[blk * W + p] = pl;
+                bases[blk * W + p] = (uint16_t)e[0];
+            }
         }
         bad = __syncthreads_or(bad);
         if (j < weff) {
             if (!bad) {
                 stream_lines<VEC, UNROLL, NTH>(
-                    dn, out, (size_t)D, band0, col, first, n1, rpp, [&](int k, uint32_t d) {
+                    rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
                         return g_packed(planes, bases, d, top, logW, (k << logq) + lane);
                     });
             } else {
                 const uint16_t* lrow = strip_lut + (size_t)j * Lz;
                 stream_lines<VEC, UNROLL, NTH>(
-                    dn, out, (size_t)D, band0, col, first, n1, rpp,
+                    rin, rout, vo, line_stride, passes,
                     [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
             }
         }
         __syncthreads();  // the tile may be restaged next
     }
+}
+
+
+// ---- fused LUT build + correction (batched requests) ------------------------------------
+
+// Writes entries [v0, v0 + n) of one LUT row (n <= 8, values in e) to global
+// memory: one 16-byte store when the 8 entries are aligned, else 16-bit stores.
+__device__ __forceinline__ void store_lut8(uint16_t* dst, const uint32_t* e, int n, bool vec16) {
+    if (vec16 && n == 8) {
+        u32x4 q;
+        q.x = e[0] | (e[1] << 16);
+        q.y = e[2] | (e[3] << 16);
+        q.z = e[4] | (e[5] << 16);
+        q.w = e[6] | (e[7] << 16);
+        *(u32x4*)dst = q;
+    } else {
+        for (int k = 0; k < n; ++k) dst[k] = (uint16_t)e[k];
+    }
+}
+
+// Computes the LUT rows of band b, detectors [d0, d0 + weff) from their
+// calibration coefficients straight into the LDS tile (raw or packed layout,
+// as the correction tile reads them) and, if `write_lut`, also into the
+// global LUT. Returns nonzero (the same on every thread) when a packed row
+// has a step outside 0..3; the LDS tile is then unusable.
+template <int VEC, int MODE>
+__device__ __forceinline__ int build_strip(const double* __restrict__ coeffs, uint16_t* lut, int D,
+                                           int L, int logW, int b, int d0, int weff,
+                                           bool write_lut, bool lut_vec, void* smem) {
+    constexpr int LOGVEC = log_vec<VEC>();
+    const int W = 1 << logW;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int logq = logW - LOGVEC;
+    const double lim = (double)L;
+    const size_t row0 = (size_t)b * (size_t)D + (size_t)d0;
+    int bad = 0;
+    if constexpr (MODE == kRaw) {
+        // Item = (detector j fastest, 8-level chunk): consecutive lanes write
+        // consecutive LDS entries.
+        uint16_t* tile = (uint16_t*)smem;
+        const int chunks = (L + 7) >> 3;
+        const int items = chunks << logW;
+        for (int it = tid; it < items; it += nt) {
+            const int j = it & (W - 1);
+            const int c = it >> logW;
+            if (j >= weff) continue;
+            const double* a = coeffs + (row0 + (size_t)j) * 4;
+            const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
+            const int v0 = c * 8;
+            const int n = min(8, L - v0);
+            uint32_t e[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                e[k] = k < n ? lut_entry(a0, a1, a2, a3, v0 + k, lim) : 0u;
+                if (k < n) tile[((v0 + k) << logW) + j] = (uint16_t)e[k];
+            }
+            if (write_lut) store_lut8(lut + (row0 + (size_t)j) * (size_t)L + v0, e, n, lut_vec);
+        }
+        __syncthreads();
+    } else {
+        // Item = (LDS position p fastest, 32-level block): consecutive lanes
+        // write consecutive packed words.
+        const int NB = (L + 31) >> 5;
+        u32x2* planes = (u32x2*)smem;
+        uint16_t* bases = (uint16_t*)(planes + (size_t)NB * W);
+        const int items = NB << logW;
+        for (int it = tid; it < items; it += nt) {
+            const int p = it & (W - 1);
+            const int blk = it >> logW;
+            const int j = ((p & ((1 << logq) - 1)) << LOGVEC) + (p >> logq);
+            if (j >= weff) continue;
+            const double* a = coeffs + (row0 + (size_t)j) * 4;
+            const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
+            const int v0 = blk * 32;
+            const int cnt = min(32, L - v0);
+            uint16_t* dst = lut + (row0 + (size_t)j) * (size_t)L + v0;
+            uint32_t lo = 0, hi = 0, prev = 0, base = 0;
+            for (int g = 0; g < cnt; g += 8) {
+                const int n = min(8, cnt - g);
+                uint32_t e[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    e[k] = k < n ? lut_entry(a0, a1, a2, a3, v0 + g + k, lim) : 0u;
+                    const int i = g + k;  // entry index within the block
+                    if (k < n) {
+                        if (i == 0) {
+                            base = e[k];
+                        } else {
+                            const uint32_t step = e[k] - prev;  // wraps when negative
+                            bad |= step > 3u;
+                            lo |= (step & 1u) << (i - 1);
+                            hi |= ((step >> 1) & 1u) << (i - 1);
+                        }
+                        prev = e[k];
+                    }
+                }
+                if (write_lut) store_lut8(dst + g, e, n, lut_vec);
+            }
+            u32x2 pl;
+            pl.x = lo;
+            pl.y = hi;
+            planes[blk * W + p] = pl;
+            bases[blk * W + p] = (uint16_t)base;
+        }
+        bad = __syncthreads_or(bad);
+    }
+    return bad;
+}
+
+// Writes the strip's LUT rows to global memory (second pass of a packed
+// strip that cannot be packed and whose tile did not write them already).
+__device__ __forceinline__ void write_strip(const double* __restrict__ coeffs, uint16_t* lut, int D,
+                                            int L, int b, int d0, int weff, bool lut_vec) {
+    const double lim = (double)L;
+    const size_t row0 = (size_t)b * (size_t)D + (size_t)d0;
+    const int chunks = (L + 7) >> 3;
+    const int items = chunks * weff;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int j = it / chunks;
+        const int v0 = (it - j * chunks) * 8;
+        const int n = min(8, L - v0);
+        const double* a = coeffs + (row0 + (size_t)j) * 4;
+        uint32_t e[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) e[k] = k < n ? lut_entry(a[0], a[1], a[2], a[3], v0 + k, lim) : 0u;
+        store_lut8(lut + (row0 + (size_t)j) * (size_t)L + v0, e, n, lut_vec);
+    }
+}
+
+// Global LUT gather that reads through the L2 (sc0), for rows this
+// workgroup has just written.
+__device__ __forceinline__ uint32_t g_glb_l2(__amdgpu_buffer_rsrc_t r, uint32_t row_off,
+                                             uint32_t dnv, uint32_t top) {
+    const uint32_t v = dnv < top ? dnv : top;
+    return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(row_off + v * 2u), 0, 1);
+}
+
+// One fused tile of a batched request: build the strip's LUT in LDS from the
+// coefficients (writing it to the global LUT too when write_lut), then
+// correct lines [n0, n1) exactly as apply_tile does.
+template <int VEC, int UNROLL, int MODE>
+__device__ __forceinline__ void fused_tile(const double* __restrict__ coeffs, const uint16_t* dn,
+                                           uint16_t* lut, uint16_t* out, int64_t N, int D, int L,
+                                           int logW, int b, int d0, int weff, int64_t n0,
+                                           int64_t n1, bool write_lut, void* smem, bool lut_vec) {
+    constexpr int LOGVEC = log_vec<VEC>();
+    const int bad = build_strip<VEC, MODE>(coeffs, lut, D, L, logW, b, d0, weff, write_lut,
+                                           lut_vec, smem);
+    if (n1 > n0) {
+        const int tid = threadIdx.x;
+        const int logq = logW - LOGVEC;
+        const int lane = tid & ((1 << logq) - 1);
+        const int rpp = blockDim.x >> logq;
+        const int j = lane * VEC;
+        const uint32_t top = (uint32_t)(L - 1);
+        const size_t tile0 = ((size_t)b * (size_t)N + (size_t)n0) * (size_t)D + (size_t)d0;
+        const uint32_t span = (uint32_t)((((size_t)(n1 - n0) - 1) * (size_t)D + (size_t)weff) * 2);
+        const __amdgpu_buffer_rsrc_t rin = make_rsrc(dn + tile0, span);
+        const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + tile0, span);
+        const uint32_t vo = (uint32_t)(((size_t)(tid >> logq) * (size_t)D + (size_t)j) * 2);
+        const uint32_t line_stride = (uint32_t)rpp * (uint32_t)D * 2u;
+        const int passes = (int)((n1 - n0 + (int64_t)rpp * UNROLL - 1) / ((int64_t)rpp * UNROLL));
+        if constexpr (MODE == kRaw) {
+            const uint16_t* tile = (const uint16_t*)smem;
+            if (j < weff) {
+                stream_lines<VEC, UNROLL, false>(
+                    rin, rout, vo, line_stride, passes,
+                    [&](int k, uint32_t d) { return g_raw(tile, d, top, logW, j + k); });
+            }
+        } else {
+            const int NB = (L + 31) >> 5;
+            const u32x2* planes = (const u32x2*)smem;
+            const uint16_t* bases = (const uint16_t*)(planes + (size_t)NB * (1 << logW));
+            if (!bad) {
+                if (j < weff) {
+                    stream_lines<VEC, UNROLL, false>(
+                        rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
+                            return g_packed(planes, bases, d, top, logW, (k << logq) + lane);
+                        });
+                }
+            } else {
+                if (!write_lut) write_strip(coeffs, lut, D, L, b, d0, weff, lut_vec);
+                __threadfence();
+                __syncthreads();
+                const size_t row0 = (size_t)b * (size_t)D + (size_t)d0;
+                const __amdgpu_buffer_rsrc_t rl =
+                    make_rsrc(lut + row0 * (size_t)L, (uint32_t)((size_t)weff * L * 2));
+                if (j < weff) {
+                    stream_lines<VEC, UNROLL, false>(
+                        rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
+                            return g_glb_l2(rl, (uint32_t)((j + k) * L * 2), d, top);
+                        });
+                }
+            }
+        }
+    }
+    __syncthreads();  // the tile may be rebuilt next
 }
 
 }  // namespace rc

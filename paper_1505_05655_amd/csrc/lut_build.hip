@@ -11,13 +11,15 @@
 namespace rc {
 
 __global__ __launch_bounds__(256) void k_lut_build(const double* __restrict__ coeffs, int64_t rows,
-                                                   int32_t levels, int32_t chunks, int32_t vec,
+                                                   int32_t levels, int32_t chunks,
+                                                   int32_t log_chunks, int32_t vec,
                                                    uint16_t* __restrict__ lut) {
     const int64_t total = rows * (int64_t)chunks;
-    const double top = (double)(levels - 1);
+    const double lim = (double)levels;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = t / chunks;
+        // Row and 8-level chunk of this thread (a shift when chunks is 2^k).
+        const int64_t row = log_chunks >= 0 ? (t >> log_chunks) : t / chunks;
         const int c = (int)(t - row * chunks);
         const double* a = coeffs + row * 4;
         const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
@@ -26,7 +28,7 @@ __global__ __launch_bounds__(256) void k_lut_build(const double* __restrict__ co
         if (vec) {
             uint32_t e[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) e[k] = lut_entry(a0, a1, a2, a3, v0 + k, top);
+            for (int k = 0; k < 8; ++k) e[k] = lut_entry(a0, a1, a2, a3, v0 + k, lim);
             u32x4 q;
             q.x = e[0] | (e[1] << 16);
             q.y = e[2] | (e[3] << 16);
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(256) void k_lut_build(const double* __restrict__ co
             *(u32x4*)dst = q;
         } else {
             for (int k = 0; k < 8 && v0 + k < levels; ++k) {
-                dst[k] = (uint16_t)lut_entry(a0, a1, a2, a3, v0 + k, top);
+                dst[k] = (uint16_t)lut_entry(a0, a1, a2, a3, v0 + k, lim);
             }
         }
     }
@@ -44,13 +46,18 @@ __global__ __launch_bounds__(256) void k_lut_build(const double* __restrict__ co
 hipError_t launch_lut_build(const double* coeffs, int64_t rows, int32_t levels, uint16_t* lut,
                             hipStream_t stream) {
     const int32_t chunks = (levels + 7) / 8;
+    int32_t log_chunks = -1;
+    if ((chunks & (chunks - 1)) == 0) {
+        log_chunks = 0;
+        while ((1 << log_chunks) < chunks) ++log_chunks;
+    }
     const bool vec = (levels % 8 == 0) && (((uintptr_t)lut & 15u) == 0);
     const int64_t total = rows * (int64_t)chunks;
     const int threads = 256;
     int64_t blocks = (total + threads - 1) / threads;
     if (blocks > (int64_t)1 << 20) blocks = (int64_t)1 << 20;  // grid-stride beyond this
     hipLaunchKernelGGL(k_lut_build, dim3((unsigned)blocks), dim3(threads), 0, stream, coeffs, rows,
-                       levels, chunks, vec ? 1 : 0, lut);
+                       levels, chunks, log_chunks, vec ? 1 : 0, lut);
     return hipGetLastError();
 }
 

@@ -40,6 +40,9 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
                      int32_t levels, int vmax, const DeviceInfo& di, ApplyParams* p,
                      size_t* lds_bytes);
 
+// Longest line chunk a tile may have (32-bit buffer offsets); < 1 if none fits.
+int64_t max_chunk_lines(int32_t detectors, int32_t threads, int32_t unroll);
+
 // LDS bytes a plan's tile needs (0 for the L2 path).
 size_t plan_lds_bytes(int path, int strip, int levels);
 

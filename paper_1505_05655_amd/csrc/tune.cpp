@@ -198,59 +198,56 @@ namespace {
 
 std::vector<rc_plan> candidates(int64_t lines, int32_t detectors, int32_t bands, int32_t levels,
                                 int vmax, const DeviceInfo& di, int effort) {
+    (void)bands;
     std::vector<rc_plan> out;
     rc_plan def;
     default_plan(lines, detectors, bands, levels, vmax, di, &def);
     out.push_back(def);
     const int64_t dcap = (int64_t)1 << clog2(std::max(detectors, 1));
-    const int vecs[] = {1, 2, 4};
-    const int threads_all[] = {256, 512, 1024};
-    const int unrolls[] = {4, 8, 16};
-    const int ks[] = {1, 2, 3, 4, 6, 8, 12, 16};
-    for (int path = 0; path < 3; ++path) {
-        for (int W = 8; W <= 256; W *= 2) {
-            if (path != RC_PATH_L2 && plan_lds_bytes(path, W, levels) > di.lds) continue;
-            if (path == RC_PATH_L2 && (W < 32 || W > 128)) continue;
+    auto add = [&](int path, int W, int vec, int threads, int unroll, int nt, int k) {
+        if (k > lines || W / vec > threads || W < vec || vec > vmax) return;
+        rc_plan p;
+        std::memset(&p, 0, sizeof p);
+        p.path = path;
+        p.strip = W;
+        p.vec = vec;
+        p.threads = threads;
+        p.unroll = unroll;
+        p.xcd_remap = 1;
+        p.nontemporal = nt;
+        p.chunk_lines = (int32_t)((lines + k - 1) / k);
+        out.push_back(p);
+    };
+    std::vector<int> vecs;
+    if (vmax >= 4) vecs.push_back(4);
+    if (vmax >= 2) vecs.push_back(2);
+    if (effort > 0 || vmax == 1) vecs.push_back(1);
+    if (effort == 0 && vecs.size() > 1) vecs.resize(1 + (vmax >= 4 ? 1 : 0));
+    const std::vector<int> threads_l = effort ? std::vector<int>{256, 512, 1024}
+                                              : std::vector<int>{512, 1024};
+    const std::vector<int> unrolls = effort ? std::vector<int>{4, 8, 16} : std::vector<int>{4, 8};
+    const std::vector<int> ks = effort ? std::vector<int>{1, 2, 3, 4, 6, 8, 12}
+                                       : std::vector<int>{1, 2, 4};
+    // LDS paths: the two widest strips that fit (the measured throughput of
+    // strip-shaped streams grows with the strip width).
+    for (int path : {RC_PATH_PACKED, RC_PATH_LDS}) {
+        std::vector<int> widths;
+        for (int W = 256; W >= 8 && widths.size() < 2; W >>= 1) {
+            if (plan_lds_bytes(path, W, levels) > di.lds) continue;
             if (W > std::max<int64_t>(dcap, 8)) continue;
-            for (int vec : vecs) {
-                if (vec > vmax || W < vec) continue;
-                if (effort == 0 && vec != std::min(vmax, 4) && vec != std::min(vmax, 2)) continue;
-                for (int threads : threads_all) {
-                    if (W / vec > threads) continue;
-                    if (path == RC_PATH_L2 && threads == 512) continue;
-                    for (int unroll : unrolls) {
-                        if (effort == 0 && unroll == 4) continue;
-                        for (int xcd = 0; xcd < 2; ++xcd) {
-                            if (effort == 0 && xcd == 0) continue;
-                            if (path == RC_PATH_L2 && xcd == 0) continue;
-                            for (int nt = 0; nt < 2; ++nt) {
-                                std::vector<int> klist;
-                                if (path == RC_PATH_L2) {
-                                    klist = {32, 64};
-                                } else {
-                                    klist.assign(std::begin(ks), std::end(ks));
-                                }
-                                for (int k : klist) {
-                                    if (k > lines) continue;
-                                    rc_plan p;
-                                    std::memset(&p, 0, sizeof p);
-                                    p.path = path;
-                                    p.strip = W;
-                                    p.vec = vec;
-                                    p.threads = threads;
-                                    p.unroll = unroll;
-                                    p.xcd_remap = xcd;
-                                    p.nontemporal = nt;
-                                    p.chunk_lines = (int32_t)((lines + k - 1) / k);
-                                    out.push_back(p);
-                                }
-                            }
-                        }
-                    }
-                }
-            }
+            widths.push_back(W);
         }
+        for (int W : widths)
+            for (int vec : vecs)
+                for (int threads : threads_l)
+                    for (int unroll : unrolls)
+                        for (int nt = 0; nt < 2; ++nt)
+                            for (int k : ks) add(path, W, vec, threads, unroll, nt, k);
     }
+    // The L2 path: a few shapes, line chunks sized so an XCD's CUs share a strip.
+    for (int W : {32, 64, 128})
+        for (int vec : vecs)
+            for (int k : {32, 64}) add(RC_PATH_L2, W, vec, 256, 8, 0, k);
     return out;
 }
 

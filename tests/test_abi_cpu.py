@@ -97,3 +97,39 @@ def test_correct_empty_is_noop():
 
 def test_correct_plan_requires_plan():
     assert L.rc_correct_plan(FAKE, FAKE * 64, 4, 4, 1, 1024, FAKE * 128, None, None) == rc.RC_EINVAL
+
+
+def _req(coeffs, dn, lut, out, lines=4, det=4, bands=1, levels=1024, reserved=0):
+    return rc.Request(coeffs, dn, lut, out, lines, det, bands, levels, reserved)
+
+
+# Request buffers (never dereferenced): coeffs 128 B at C, lut 8 KiB at T,
+# dn/out 32 B at I/O, second request shifted by S.
+C, T, I, O, S = 0x100000, 0x200000, 0x300000, 0x400000, 0x1000000
+
+
+@pytest.mark.parametrize("reqs", [
+    [_req(C, I, T, O, reserved=1)],                       # reserved field set
+    [_req(None, I, T, O)],                                # NULL coeffs
+    [_req(C, I, T, O, levels=1)],                         # bad levels
+    [_req(C, I, T, O, lines=-1)],                         # negative lines
+    [_req(C, I, T, I + 2)],                               # out partially overlaps dn
+    [_req(C, I, C + 8, O)],                               # lut overlaps coeffs
+    [_req(C, T, T, O)],                                   # lut overlaps dn
+    [_req(C, I, T, O), _req(C + S, I + S, T + S, O)],     # two requests write one out
+    [_req(C, I, T, O), _req(C + S, O, T + S, O + S)],     # output of one is input of another
+    [_req(C, I, T, O), _req(C + S, I + S, T, O + S)],     # shared LUT written twice
+])
+def test_batch_rejects(reqs):
+    arr = (rc.Request * len(reqs))(*reqs)
+    h = ctypes.c_void_p()
+    assert L.rc_batch_create(arr, len(reqs), 0, ctypes.byref(h)) == rc.RC_EINVAL
+    assert not h.value
+
+
+def test_batch_null_args():
+    h = ctypes.c_void_p()
+    assert L.rc_batch_create(None, 3, 0, ctypes.byref(h)) == rc.RC_EINVAL
+    assert L.rc_batch_create(None, -1, 0, ctypes.byref(h)) == rc.RC_EINVAL
+    assert L.rc_batch_run(None, None) == rc.RC_EINVAL
+    L.rc_batch_destroy(None)
