@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time spent timing the oracle")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-request batch leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-jobs", type=int, default=300)
+    ap.add_argument("--serve-qps", type=float, default=150.0)
     ap.add_argument("--batch-requests", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 4 device-to-device copies of MIB MiB (hardware counter "
@@ -138,6 +141,152 @@ def bench_batch(args, torch, rc, dev):
         "bit_exact_batched_vs_plain": same,
         "bit_exact_oracle_sample": oracle_ok, "oracle_sample_requests": [int(i) for i in sample],
         "setup_s": round(gen_s, 1),
+    }
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    f = int(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def bench_serve(args, torch, rc, dev):
+    """Workload 4: Poisson arrivals of 1-600 Mpix jobs from pinned host memory,
+    through rc_server (continuous batching), and through a plain server that
+    runs one job at a time (copy in, rc_lut_build, rc_correct, copy out, sync)."""
+    import threading
+
+    import gen
+    import oracle
+
+    trace = gen.serve_trace(args.serve_jobs, qps=args.serve_qps)
+    max_px = max(j.pixels for _, j in trace)
+    t0 = time.time()
+    # Host data: per bit depth one pinned pool of seeded DN holding the largest
+    # job; a job's image is the pool's first pixels in its own shape. Outputs
+    # of unverified jobs share one pinned sink per depth.
+    pools, sinks = {}, {}
+    for depth, kind in ((10, gen.DN_GAUSS_SAT10), (12, gen.DN_SCENE12)):
+        pool = rc.pinned_empty((max_px,), np.uint16)
+        rows = max_px // 4096 + 1
+        tmp = gen.dn(gen.BASE_SEED + 4, 4, 1000 + depth, kind, 1, rows, 4096)
+        pool[:] = tmp.reshape(-1)[:max_px]
+        pools[depth] = pool
+        sinks[depth] = rc.pinned_empty((max_px,), np.uint16)
+    depth_of = lambda j: 10 if j.levels == 1024 else 12
+    coeffs = []
+    for _, j in trace:
+        c = rc.pinned_empty((j.bands, j.detectors, 4), np.float64)
+        c[...] = j.coeffs()
+        coeffs.append(c)
+    # Jobs checked against the oracle get outputs of their own.
+    small = sorted(range(len(trace)), key=lambda i: trace[i][1].pixels)[:6]
+    verify = set(small) | set(range(0, len(trace), max(1, len(trace) // 4)))
+    outs = {i: rc.pinned_empty(trace[i][1].pixels, np.uint16) for i in verify}
+    setup_s = time.time() - t0
+
+    def dn_of(i):
+        j = trace[i][1]
+        return pools[depth_of(j)][:j.pixels].reshape(j.bands, j.lines, j.detectors)
+
+    def out_of(i):
+        j = trace[i][1]
+        buf = outs[i] if i in outs else sinks[depth_of(j)][:j.pixels]
+        return buf.reshape(j.bands, j.lines, j.detectors)
+
+    # Pinned copy bandwidth, for the PCIe ceiling.
+    probe = pools[10][:256 << 20] if max_px >= (256 << 20) else pools[10]
+    d_t = torch.empty(probe.shape, dtype=torch.int16, device=dev)
+    src = torch.from_numpy(probe.view(np.int16))
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    for _ in range(3):
+        d_t.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d_gbs = 3 * probe.nbytes / (time.perf_counter() - c0) / 1e9
+    dst = torch.from_numpy(sinks[10][:probe.size].view(np.int16))
+    c0 = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(d_t, non_blocking=True)
+    torch.cuda.synchronize()
+    d2h_gbs = 3 * probe.nbytes / (time.perf_counter() - c0) / 1e9
+    del d_t
+
+    def run_server():
+        srv = rc.Server()
+        ids = [None] * len(trace)
+        start = time.perf_counter()
+
+        def client():
+            for i, (t_arr, j) in enumerate(trace):
+                delay = start + t_arr - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                ids[i] = srv.submit(coeffs[i], dn_of(i), out_of(i), j.levels)
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        stats = [srv.wait(ids[i]) for i in range(len(trace))]
+        info = srv.info()
+        srv.close()
+        return stats, info
+
+    stats, info = run_server()
+    ok = all(st["status"] == rc.RC_OK for st in stats)
+    lat = [st["latency_s"] for st in stats]
+    first = min(st["submit_s"] for st in stats)
+    last = max(st["done_s"] for st in stats)
+    px = sum(j.pixels for _, j in trace)
+    o = oracle.get()
+    exact = True
+    for i in sorted(verify):
+        j = trace[i][1]
+        w = o.correct(dn_of(i), o.lut_build(coeffs[i], j.levels))
+        exact &= bool(np.array_equal(out_of(i), w))
+
+    # Plain server: the same arrivals, one job at a time on one stream.
+    stream = torch.cuda.Stream(device=dev)
+    plain_lat, plain_done = [], []
+    start = time.perf_counter()
+    for i, (t_arr, j) in enumerate(trace):
+        delay = start + t_arr - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        with torch.cuda.stream(stream):
+            c_t = torch.from_numpy(coeffs[i]).to(dev, non_blocking=True)
+            d_in = torch.from_numpy(dn_of(i).view(np.int16)).to(dev, non_blocking=True)
+            lut = torch.empty((j.bands, j.detectors, j.levels), dtype=torch.int16, device=dev)
+            d_out = torch.empty_like(d_in)
+            rc.rc_lut_build(c_t, j.bands, j.detectors, j.levels, lut, stream)
+            rc.rc_correct(d_in, lut, j.lines, j.detectors, j.bands, j.levels, d_out, stream)
+            torch.from_numpy(out_of(i).view(np.int16)).copy_(d_out, non_blocking=True)
+        stream.synchronize()
+        now = time.perf_counter()
+        plain_lat.append(now - (start + t_arr))
+        plain_done.append(now - start)
+        del c_t, d_in, lut, d_out
+    torch.cuda.empty_cache()
+    plain_span = plain_done[-1] - trace[0][0]
+    return {
+        "workload": f"{len(trace)} jobs, Poisson arrivals at {args.serve_qps:g} jobs/s, "
+                    "log-uniform 1-600 Mpix, 1-4 bands, 10/12-bit, pinned host buffers",
+        "pixels": px, "offered_gpix_s": round(px / trace[-1][0] / 1e9, 2),
+        "served_gpix_s": round(px / (last - first) / 1e9, 2),
+        "p50_latency_ms": round(percentile(lat, 50) * 1e3, 2),
+        "p99_latency_ms": round(percentile(lat, 99) * 1e3, 2),
+        "plain_gpix_s": round(px / plain_span / 1e9, 2),
+        "plain_p50_latency_ms": round(percentile(plain_lat, 50) * 1e3, 2),
+        "plain_p99_latency_ms": round(percentile(plain_lat, 99) * 1e3, 2),
+        "pinned_h2d_gb_s": round(h2d_gbs, 1), "pinned_d2h_gb_s": round(d2h_gbs, 1),
+        "pcie_bound_gpix_s": round(min(h2d_gbs, d2h_gbs) / 2, 2),
+        "quanta": info["quanta"], "tiles": info["tiles"],
+        "all_ok": ok, "bit_exact_oracle_sample": exact,
+        "oracle_sample_jobs": sorted(int(i) for i in verify), "setup_s": round(setup_s, 1),
     }
 
 
@@ -267,11 +416,17 @@ def main():
             bit_exact = bool(np.array_equal(got, want) and np.array_equal(got_lut, want_lut))
 
     batch_res = None
+    del dn_t, out_t, lut_t, c_t
+    torch.cuda.empty_cache()
     if not args.no_batch:
-        del dn_t, out_t, lut_t, c_t
         torch.cuda.empty_cache()
         print("[bench] batch leg", file=sys.stderr, flush=True)
         batch_res = bench_batch(args, torch, rc, dev)
+
+    serve_res = None
+    if not args.no_serve:
+        print("[bench] serve leg", file=sys.stderr, flush=True)
+        serve_res = bench_serve(args, torch, rc, dev)
 
     props = torch.cuda.get_device_properties(dev)
     line = {
@@ -305,6 +460,7 @@ def main():
             "lut_build_gb_s": round(build_bytes / (statistics.mean(build_ms) * 1e-3) / 1e9, 1),
         },
         "batch": batch_res,
+        "serve": serve_res,
         "device": {"name": props.name, "cus": props.multi_processor_count,
                    "hbm_gib": round(props.total_memory / 2 ** 30, 1),
                    "arch": getattr(props, "gcnArchName", "")},

@@ -210,6 +210,99 @@ rc_status rc_batch_info(const rc_batch* b, rc_batch_stats* stats);
 /* Frees the batch (its runs must have completed). NULL is ignored. */
 void rc_batch_destroy(rc_batch* b);
 
+/* ---- serving: continuous batching of jobs from host memory ----------------------------- */
+
+/*
+ * The paper's framework (§II) lets clients submit a processing task with its
+ * data to a remote GPU server and receive the results. An rc_server is that
+ * server's GPU side, in-process: jobs arrive at any time with host buffers;
+ * a scheduler thread admits each job when its device bytes fit the server's
+ * arena and a job slot is free (first come, first served), copies it in
+ * piece by piece on a host-to-device stream, runs the tiles of every piece
+ * that has arrived, from all admitted jobs together, as quanta of one
+ * persistent kernel (continuous batching), and copies each finished piece
+ * back on a device-to-host stream. Results are bit-identical to rc_lut_build
+ * + rc_correct on the same job.
+ */
+typedef struct rc_server rc_server;
+
+typedef struct {
+    uint64_t arena_bytes;      /* device memory for admitted jobs; 0 = half the free memory */
+    int32_t max_jobs;          /* jobs admitted at once; 0 = 64 */
+    int32_t max_quantum_tiles; /* tiles per persistent launch; 0 = 4096 */
+    int64_t piece_pixels;      /* pixels per copy piece; 0 = 16 Mi */
+    int32_t flags;             /* must be 0 */
+    int32_t reserved;          /* must be 0 */
+} rc_server_opts;
+
+/*
+ * A job in host memory. Layouts as for rc_lut_build / rc_correct. Use pinned
+ * memory (rc_host_alloc) for full-speed, asynchronous copies; pageable
+ * buffers work but make the scheduler wait on each copy. The caller owns the
+ * buffers and must keep them valid, and not modify dn/coeffs, until
+ * rc_server_wait or rc_server_poll reports the job finished.
+ */
+typedef struct {
+    const double* coeffs;  /* host, [bands][detectors][4] */
+    const uint16_t* dn;    /* host, [bands][lines][detectors] */
+    uint16_t* out;         /* host, [bands][lines][detectors], written */
+    uint16_t* lut;         /* host, [bands][detectors][levels], written; NULL: not returned */
+    int64_t lines;
+    int32_t detectors;
+    int32_t bands;
+    int32_t levels;
+    int32_t reserved;      /* must be 0 */
+} rc_host_job;
+
+typedef struct {
+    double submit_s;   /* host steady-clock seconds: rc_server_submit */
+    double admit_s;    /* admitted (device memory reserved, copies in enqueued) */
+    double start_s;    /* first tile issued to the GPU */
+    double done_s;     /* scheduler saw the last copy back complete */
+    double latency_s;  /* done_s - submit_s */
+    int64_t pixels;
+    int32_t status;    /* rc_status of the job */
+    int32_t reserved;
+} rc_job_stats;
+
+typedef struct {
+    uint64_t submitted, completed;
+    uint64_t quanta, tiles;    /* persistent launches and tiles issued */
+    uint64_t pixels;           /* pixels of completed jobs */
+    uint64_t arena_bytes, arena_used;
+    int32_t pending, active;   /* jobs waiting for admission / admitted */
+    int32_t waiters;           /* threads blocked in rc_server_wait */
+    int32_t reserved;
+} rc_server_stats;
+
+/* Creates a server on the current device (arena, streams, scheduler thread).
+ * o may be NULL for defaults. Errors: RC_EINVAL, RC_ENOMEM, RC_EHIP. */
+rc_status rc_server_create(const rc_server_opts* o, rc_server** out);
+
+/* Queues a job; returns at once with its id. RC_EINVAL for bad jobs,
+ * RC_ENOMEM if the job can never fit the arena, RC_ECLOSED after
+ * rc_server_destroy began, RC_EHIP if the server failed. */
+rc_status rc_server_submit(rc_server* s, const rc_host_job* j, uint64_t* job_id);
+
+/* Blocks until the job finished; returns its status (RC_OK, RC_ECLOSED if the
+ * server shut down before admitting it, RC_EHIP on a device error) and fills
+ * st (may be NULL). A job id can be waited for (or polled to completion) once. */
+rc_status rc_server_wait(rc_server* s, uint64_t job_id, rc_job_stats* st);
+
+/* Non-blocking: RC_EBUSY while the job runs, else as rc_server_wait. */
+rc_status rc_server_poll(rc_server* s, uint64_t job_id, rc_job_stats* st);
+
+rc_status rc_server_info(rc_server* s, rc_server_stats* st);
+
+/* Stops admitting, lets admitted jobs finish, completes never-admitted jobs
+ * with RC_ECLOSED, then frees everything. Must not race with other calls on s
+ * except waiters of its jobs. NULL is ignored. */
+void rc_server_destroy(rc_server* s);
+
+/* Pinned host memory for job buffers (hipHostMalloc); NULL on failure. */
+void* rc_host_alloc(size_t bytes);
+void rc_host_free(void* p);
+
 #ifdef __cplusplus
 }
 #endif

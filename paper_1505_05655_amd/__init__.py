@@ -79,6 +79,41 @@ class BatchStats(ctypes.Structure):
 
 RC_BATCH_NO_GRAPH = 1
 
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_jobs", ctypes.c_int32),
+                ("max_quantum_tiles", ctypes.c_int32), ("piece_pixels", ctypes.c_int64),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class HostJob(ctypes.Structure):
+    _fields_ = [("coeffs", ctypes.c_void_p), ("dn", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("lut", ctypes.c_void_p), ("lines", ctypes.c_int64), ("detectors", ctypes.c_int32),
+                ("bands", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class JobStats(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("latency_s", ctypes.c_double), ("pixels", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("quanta", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
+                ("pixels", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_used", ctypes.c_uint64), ("pending", ctypes.c_int32),
+                ("active", ctypes.c_int32), ("waiters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 _lib.rc_status_str.argtypes = [ctypes.c_int]
 _lib.rc_status_str.restype = ctypes.c_char_p
@@ -112,6 +147,22 @@ _lib.rc_batch_info.argtypes = [_vp, ctypes.POINTER(BatchStats)]
 _lib.rc_batch_info.restype = ctypes.c_int
 _lib.rc_batch_destroy.argtypes = [_vp]
 _lib.rc_batch_destroy.restype = None
+_lib.rc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
+_lib.rc_server_create.restype = ctypes.c_int
+_lib.rc_server_submit.argtypes = [_vp, ctypes.POINTER(HostJob), ctypes.POINTER(ctypes.c_uint64)]
+_lib.rc_server_submit.restype = ctypes.c_int
+_lib.rc_server_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(JobStats)]
+_lib.rc_server_wait.restype = ctypes.c_int
+_lib.rc_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(JobStats)]
+_lib.rc_server_poll.restype = ctypes.c_int
+_lib.rc_server_info.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+_lib.rc_server_info.restype = ctypes.c_int
+_lib.rc_server_destroy.argtypes = [_vp]
+_lib.rc_server_destroy.restype = None
+_lib.rc_host_alloc.argtypes = [ctypes.c_size_t]
+_lib.rc_host_alloc.restype = _vp
+_lib.rc_host_free.argtypes = [_vp]
+_lib.rc_host_free.restype = None
 
 
 def lib():
@@ -245,6 +296,87 @@ class Batch:
     def close(self):
         if self.handle:
             rc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host_ptr(x):
+    """Address of a host buffer: numpy array, CPU tensor or int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, torch.Tensor):
+        if x.is_cuda or not x.is_contiguous():
+            raise ValueError("expected a contiguous host tensor")
+        return x.data_ptr() if x.numel() else None
+    if not x.flags.c_contiguous:
+        raise ValueError("expected a C-contiguous array")
+    return x.ctypes.data if x.size else None
+
+
+def pinned_empty(shape, dtype):
+    """A numpy array in pinned host memory (backed by a pinned torch tensor)."""
+    import numpy as np
+    tdtype = {np.dtype(np.uint16): torch.int16, np.dtype(np.int16): torch.int16,
+              np.dtype(np.float64): torch.float64}[np.dtype(dtype)]
+    t = torch.empty(shape, dtype=tdtype, pin_memory=True)
+    return t.numpy().view(dtype)
+
+
+class Server:
+    """In-process serving runtime (rc_server): submit host jobs, wait for them."""
+
+    def __init__(self, arena_bytes=0, max_jobs=0, max_quantum_tiles=0, piece_pixels=0):
+        opts = ServerOpts(arena_bytes, max_jobs, max_quantum_tiles, piece_pixels, 0, 0)
+        h = _vp()
+        _check(_lib.rc_server_create(ctypes.byref(opts), ctypes.byref(h)), "rc_server_create")
+        self.handle = h.value
+        self._keep = {}
+
+    def submit(self, coeffs, dn, out, levels, lut=None):
+        """coeffs [B, D, 4] float64, dn/out [B, N, D] uint16 host arrays (pinned
+        preferred), optional lut [B, D, L] uint16. Returns the job id."""
+        B, N, D = dn.shape
+        job = HostJob(_host_ptr(coeffs), _host_ptr(dn), _host_ptr(out), _host_ptr(lut), N, D, B,
+                      levels, 0)
+        jid = ctypes.c_uint64(0)
+        _check(_lib.rc_server_submit(self.handle, ctypes.byref(job), ctypes.byref(jid)),
+               "rc_server_submit")
+        self._keep[jid.value] = (coeffs, dn, out, lut)
+        return jid.value
+
+    def wait(self, job_id):
+        st = JobStats()
+        status = _lib.rc_server_wait(self.handle, job_id, ctypes.byref(st))
+        self._keep.pop(job_id, None)
+        d = st.as_dict()
+        d["status"] = status
+        return d
+
+    def poll(self, job_id):
+        st = JobStats()
+        status = _lib.rc_server_poll(self.handle, job_id, ctypes.byref(st))
+        if status == RC_EBUSY:
+            return None
+        self._keep.pop(job_id, None)
+        d = st.as_dict()
+        d["status"] = status
+        return d
+
+    def info(self):
+        st = ServerStats()
+        _check(_lib.rc_server_info(self.handle, ctypes.byref(st)), "rc_server_info")
+        return st.as_dict()
+
+    def close(self):
+        if self.handle:
+            _lib.rc_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,56 @@
+// Descriptors and launchers of the persistent tile kernel shared by the batch
+// and serving runtimes (internal to librc).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rc.h"
+
+namespace rc {
+
+constexpr int kBatchThreads = 1024;
+constexpr int kBatchUnroll = 4;
+constexpr size_t kBatchLds = 80 * 1024;
+
+// Per-request descriptor, resident in device memory.
+struct BatchReq {
+    const double* coeffs;
+    const uint16_t* dn;
+    uint16_t* lut;
+    uint16_t* out;
+    int64_t lines;
+    int32_t detectors;
+    int32_t bands;
+    int32_t levels;
+    int32_t log_strip;
+    int32_t vec;
+    int32_t mode;     // kRaw / kGlobal / kPacked
+    int32_t lut_vec;  // LUT rows allow 16-byte loads/stores
+    int32_t fused;    // tiles build their LUT strip in LDS (mode kRaw / kPacked)
+};
+
+struct BatchTile {
+    int32_t req;
+    int32_t band;
+    int32_t d0;
+    int32_t pad;
+    int64_t n0;
+    int64_t n1;
+};
+
+// Persistent correction kernel over `ntiles` tiles (grid workgroups pop
+// tiles from counters[0]; counters must be zero before the first launch and
+// are rearmed by the kernel itself).
+hipError_t launch_batch_apply(const BatchReq* reqs, const BatchTile* tiles, int32_t ntiles,
+                              unsigned int* counters, int grid, size_t lds, hipStream_t stream);
+
+// Sets the persistent kernel's dynamic LDS limit on the current device.
+hipError_t prepare_batch_kernel(size_t lds);
+
+// Fills q's strip shape and mode from a plain-path plan, fitted to the
+// persistent kernel's workgroup size and LDS budget.
+void fit_request_plan(const rc_plan& plan, int levels, size_t lds_cap, BatchReq* q);
+
+}  // namespace rc

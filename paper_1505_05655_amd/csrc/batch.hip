@@ -27,42 +27,13 @@
 #include <new>
 #include <vector>
 
+#include "batch.h"
 #include "device_ops.h"
 #include "kernels.h"
 #include "rc.h"
 #include "runtime.h"
 
 namespace rc {
-
-// Per-request descriptor, resident in device memory.
-struct BatchReq {
-    const double* coeffs;
-    const uint16_t* dn;
-    uint16_t* lut;
-    uint16_t* out;
-    int64_t lines;
-    int32_t detectors;
-    int32_t bands;
-    int32_t levels;
-    int32_t log_strip;
-    int32_t vec;
-    int32_t mode;     // kRaw / kGlobal / kPacked
-    int32_t lut_vec;  // LUT rows allow 16-byte loads/stores
-    int32_t fused;    // tiles build their LUT strip in LDS (mode kRaw / kPacked)
-};
-
-struct BatchTile {
-    int32_t req;
-    int32_t band;
-    int32_t d0;
-    int32_t pad;
-    int64_t n0;
-    int64_t n1;
-};
-
-constexpr int kBatchThreads = 1024;
-constexpr int kBatchUnroll = 4;
-constexpr size_t kBatchLds = 80 * 1024;
 
 __global__ __launch_bounds__(256) void k_lut_build_batch(const BatchReq* __restrict__ reqs,
                                                          const int64_t* __restrict__ prefix,
@@ -160,6 +131,34 @@ __global__ __launch_bounds__(kBatchThreads) void k_apply_batch(const BatchReq* _
     }
 }
 
+hipError_t launch_batch_apply(const BatchReq* reqs, const BatchTile* tiles, int32_t ntiles,
+                              unsigned int* counters, int grid, size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL(k_apply_batch, dim3((unsigned)grid), dim3(kBatchThreads), lds, stream, reqs,
+                       tiles, ntiles, counters);
+    return hipGetLastError();
+}
+
+hipError_t prepare_batch_kernel(size_t lds) {
+    return hipFuncSetAttribute((const void*)k_apply_batch,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+void fit_request_plan(const rc_plan& plan_in, int levels, size_t lds_cap, BatchReq* q) {
+    rc_plan p = plan_in;
+    while (p.path != RC_PATH_L2 && plan_lds_bytes(p.path, p.strip, levels) > lds_cap &&
+           p.strip > p.vec)
+        p.strip >>= 1;
+    if (p.path != RC_PATH_L2 && plan_lds_bytes(p.path, p.strip, levels) > lds_cap)
+        p.path = RC_PATH_L2;
+    if (p.strip / p.vec > kBatchThreads) p.strip = kBatchThreads * p.vec;
+    int lw = 0;
+    while ((1 << (lw + 1)) <= p.strip) ++lw;
+    q->log_strip = lw;
+    q->vec = p.vec;
+    q->mode = p.path == RC_PATH_LDS ? kRaw : (p.path == RC_PATH_PACKED ? kPacked : kGlobal);
+    q->fused = q->mode == kGlobal ? 0 : 1;
+}
+
 }  // namespace rc
 
 using namespace rc;
@@ -226,9 +225,8 @@ hipError_t enqueue(const rc_batch* b, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     if (b->ntiles > 0) {
-        hipLaunchKernelGGL(k_apply_batch, dim3((unsigned)b->slots), dim3(kBatchThreads), b->lds, s,
-                           b->d_reqs, b->d_tiles, b->ntiles, b->d_counters);
-        return hipGetLastError();
+        return launch_batch_apply(b->d_reqs, b->d_tiles, b->ntiles, b->d_counters, b->slots,
+                                  b->lds, s);
     }
     return hipSuccess;
 }
@@ -301,19 +299,8 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
             rc_plan p;
             if (!tuned_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p))
                 default_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p);
-            // Fit the plan to the batch kernel: fixed workgroup size, LDS budget.
-            while (p.path != RC_PATH_L2 && plan_lds_bytes(p.path, p.strip, r.levels) > lds_cap &&
-                   p.strip > p.vec)
-                p.strip >>= 1;
-            if (p.path != RC_PATH_L2 && plan_lds_bytes(p.path, p.strip, r.levels) > lds_cap)
-                p.path = RC_PATH_L2;
-            if (p.strip / p.vec > kBatchThreads) p.strip = kBatchThreads * p.vec;
-            int lw = 0;
-            while ((1 << (lw + 1)) <= p.strip) ++lw;
-            q.log_strip = lw;
-            q.vec = p.vec;
-            q.mode = p.path == RC_PATH_LDS ? kRaw : (p.path == RC_PATH_PACKED ? kPacked : kGlobal);
-            q.fused = q.mode == kGlobal ? 0 : 1;
+            fit_request_plan(p, r.levels, lds_cap, &q);
+            const int lw = q.log_strip;
             // One tile per (band, strip) and line chunk; strips of up to 8192
             // lines are not split (re-staging the LUT strip per chunk would
             // re-read it), longer ones are cut into chunks of at most 8192.
@@ -396,10 +383,7 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
     if ((e = hipMemsetAsync(bt->d_counters, 0, 2 * sizeof(unsigned int), bt->cap)) != hipSuccess)
         return fail(e);
     if ((e = hipStreamSynchronize(bt->cap)) != hipSuccess) return fail(e);
-    if ((e = hipFuncSetAttribute((const void*)k_apply_batch,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap)) !=
-        hipSuccess)
-        return fail(e);
+    if ((e = prepare_batch_kernel(lds_cap)) != hipSuccess) return fail(e);
     if (bt->use_graph) {
         if ((e = hipStreamBeginCapture(bt->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return fail(e);

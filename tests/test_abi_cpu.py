@@ -133,3 +133,18 @@ def test_batch_null_args():
     assert L.rc_batch_create(None, -1, 0, ctypes.byref(h)) == rc.RC_EINVAL
     assert L.rc_batch_run(None, None) == rc.RC_EINVAL
     L.rc_batch_destroy(None)
+
+
+def test_server_argument_checks():
+    h = ctypes.c_void_p()
+    bad = rc.ServerOpts(0, 0, 0, 0, 0, 7)  # reserved must be 0
+    assert L.rc_server_create(ctypes.byref(bad), ctypes.byref(h)) == rc.RC_EINVAL
+    bad = rc.ServerOpts(0, -1, 0, 0, 0, 0)
+    assert L.rc_server_create(ctypes.byref(bad), ctypes.byref(h)) == rc.RC_EINVAL
+    assert L.rc_server_create(None, None) == rc.RC_EINVAL
+    jid = ctypes.c_uint64()
+    job = rc.HostJob(FAKE, FAKE, FAKE, None, 4, 4, 1, 1024, 0)
+    assert L.rc_server_submit(None, ctypes.byref(job), ctypes.byref(jid)) == rc.RC_EINVAL
+    assert L.rc_server_wait(None, 1, None) == rc.RC_EINVAL
+    assert L.rc_server_poll(None, 1, None) == rc.RC_EINVAL
+    L.rc_server_destroy(None)
