@@ -125,23 +125,40 @@ template <bool NTH> struct Buf<4, NTH> {
     }
 };
 
-// Streams `passes` passes over a tile's lines: in each pass a lane loads its
-// VEC pixels from UNROLL lines (line_stride bytes apart) before it gathers
-// and stores any of them, so many loads are in flight per lane.
+// Streams `passes` passes over a tile's lines. In each pass a lane handles
+// its VEC pixels of UNROLL lines (line_stride bytes apart). Software
+// pipelined with two register sets used alternately: the loads of pass k+1
+// are issued before pass k is gathered and stored, so a wave's memory
+// latency overlaps its own gather work (no register copies between the sets,
+// which would force a wait on the prefetched loads). The prefetch past the
+// last pass falls outside the buffer range (loads of 0); offsets stay below
+// 2^31 because tiles are sized with two passes of slack.
 template <int VEC, int UNROLL, bool NTH, typename G>
 __device__ __forceinline__ void stream_lines(__amdgpu_buffer_rsrc_t rin,
                                              __amdgpu_buffer_rsrc_t rout, uint32_t vo,
                                              uint32_t line_stride, int passes, G gather) {
     typedef typename Px<VEC>::T T;
-    uint32_t so = 0;
-    for (int k = 0; k < passes; ++k) {
-        T w[UNROLL];
+    const uint32_t pass_bytes = UNROLL * line_stride;
+    T a[UNROLL], b[UNROLL];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) w[u] = Buf<VEC, NTH>::ld(rin, vo, so + u * line_stride);
+    for (int u = 0; u < UNROLL; ++u) a[u] = Buf<VEC, NTH>::ld(rin, vo, u * line_stride);
+    uint32_t so = 0;
+    for (int k = 0; k < passes; k += 2) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-            Buf<VEC, NTH>::st(rout, vo, so + u * line_stride, map_px<VEC>(w[u], gather));
-        so += UNROLL * line_stride;
+            b[u] = Buf<VEC, NTH>::ld(rin, vo, so + pass_bytes + u * line_stride);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            Buf<VEC, NTH>::st(rout, vo, so + u * line_stride, map_px<VEC>(a[u], gather));
+        if (k + 1 >= passes) break;
+        so += pass_bytes;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            a[u] = Buf<VEC, NTH>::ld(rin, vo, so + pass_bytes + u * line_stride);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            Buf<VEC, NTH>::st(rout, vo, so + u * line_stride, map_px<VEC>(b[u], gather));
+        so += pass_bytes;
     }
 }
 
