@@ -298,9 +298,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload_name, algo_bytes):
+def load_traffic(workload_name):
     """HBM bytes per correction launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are each scaled by what the
+    same counter reads for a plain device copy of known size on the same GPU.
+    """
     path = os.path.join(PROFILES, f"lut_apply_{workload_name}_pmc.json")
     if not os.path.exists(path):
         return None
@@ -308,7 +312,10 @@ def load_traffic(workload_name, algo_bytes):
         d = json.load(fh)
     if d.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    cal = d["copy_calibration"]
+    fetch_scale = cal["bytes_each_way"] / (cal["fetch_kib"] * 1024.0)
+    write_scale = cal["bytes_each_way"] / (cal["write_kib"] * 1024.0)
+    return round(d["fetch_kib"] * 1024.0 * fetch_scale + d["write_kib"] * 1024.0 * write_scale)
 
 
 def cpu_model():
@@ -447,7 +454,7 @@ def main():
                    "plan": plan.as_dict(), "plan_tuned": tuned},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(s.name, apply_bytes),
+                     "traffic": load_traffic(s.name),
                      "kernel": "lut_apply", "algorithmic_bytes": apply_bytes},
         "cpu_baseline": cpu,
         "bit_exact": bit_exact,

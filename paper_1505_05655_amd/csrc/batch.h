@@ -13,6 +13,8 @@ namespace rc {
 constexpr int kBatchThreads = 1024;
 constexpr int kBatchUnroll = 4;
 constexpr size_t kBatchLds = 80 * 1024;
+// Resident workgroups per CU the batch launch aims for (2048 threads per CU).
+constexpr int kBatchPerCu = 2048 / kBatchThreads;
 
 // Per-request descriptor, resident in device memory.
 struct BatchReq {

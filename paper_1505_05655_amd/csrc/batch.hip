@@ -351,8 +351,8 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
     bt->build_items = prefix.back();
     bt->lds = lds_cap;
     bt->use_graph = !(flags & RC_BATCH_NO_GRAPH);
-    bt->slots = std::max(1, di->cus) * (int)std::max<size_t>(1, std::min<size_t>(
-                                                                    2, di->lds_per_cu / lds_cap));
+    bt->slots = std::max(1, di->cus) *
+                (int)std::max<size_t>(1, std::min<size_t>(kBatchPerCu, di->lds_per_cu / lds_cap));
     hipError_t e = hipSuccess;
     auto fail = [&](hipError_t err) {
         release(bt);

@@ -22,10 +22,14 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // round half away from zero and clamp to [0, L-1]. `lim` is (double)L.
 // The rounding and clamp are done as: c = min(max(acc, 0), L) in binary64
 // (maxNum sends NaN to 0, -Inf and every negative to 0, +Inf to L), then
-// i = trunc(c) and r = i + (c - i >= 0.5), then min(r, L-1). For c in
-// [0, L] the difference c - i is exact, so r equals round-half-away(acc)
-// whenever 0 <= acc <= L, and the integer clamp gives the defined value at
-// both ends.
+// r = trunc(c + h) with h = 0.5 - 2^-54 (the double just below 1/2), then
+// min(r, L-1). For 0 <= c < 2^52, trunc(fl(c + h)) is round-half-away(c):
+// if frac(c) >= 1/2 the exact sum is at least n - 2^-54 for n = ceil(c), and
+// it only falls below n when c = n - 1/2, where n - 2^-54 rounds up to n
+// (a tie to even at n = 1, nearer n above); if frac(c) < 1/2 the exact sum
+// is at most floor(c) + 1 - ulp(c) - 2^-54, more than half an ulp below
+// floor(c) + 1, so it cannot round up to it. With plain 1/2 instead of h,
+// c = 1/2 - 2^-54 would round to 1.
 __device__ __forceinline__ uint32_t lut_entry(double a0, double a1, double a2, double a3, int v,
                                               double lim) {
     const double x = (double)v;
@@ -37,8 +41,7 @@ __device__ __forceinline__ uint32_t lut_entry(double a0, double a1, double a2, d
     acc = acc * x;
     acc = acc + a0;
     const double c = __builtin_fmin(__builtin_fmax(acc, 0.0), lim);
-    const uint32_t i = (uint32_t)c;
-    const uint32_t r = i + ((c - (double)i) >= 0.5 ? 1u : 0u);
+    const uint32_t r = (uint32_t)(c + 0x1.fffffffffffffp-2);
     const uint32_t top = (uint32_t)lim - 1u;
     return r < top ? r : top;
 }

@@ -631,7 +631,7 @@ rc_status rc_server_create(const rc_server_opts* o, rc_server** out) {
     s->di = di;
     s->lds = std::min(kBatchLds, di->lds);
     s->grid = std::max(1, di->cus) *
-              (int)std::max<size_t>(1, std::min<size_t>(2, di->lds_per_cu / s->lds));
+              (int)std::max<size_t>(1, std::min<size_t>(kBatchPerCu, di->lds_per_cu / s->lds));
     hipError_t e = hipSuccess;
     auto fail = [&](hipError_t err) {
         release_server(s);
