@@ -493,50 +493,59 @@ __device__ __forceinline__ int build_strip(const double* __restrict__ coeffs, ui
         }
         __syncthreads();
     } else {
-        // Item = (LDS position p fastest, 32-level block): consecutive lanes
-        // write consecutive packed words.
+        // A wave evaluates one detector row at a time, 16 blocks of 32 levels
+        // per pass: lane 4g + q computes levels 32 (16 r + g) + 8q .. + 7, so
+        // the wave's global LUT stores cover 1 KiB of the row contiguously.
+        // The four lanes of a block merge their step bits by lane shuffles.
         const int NB = (L + 31) >> 5;
         u32x2* planes = (u32x2*)smem;
         uint16_t* bases = (uint16_t*)(planes + (size_t)NB * W);
-        const int items = NB << logW;
-        for (int it = tid; it < items; it += nt) {
-            const int p = it & (W - 1);
-            const int blk = it >> logW;
-            const int j = ((p & ((1 << logq) - 1)) << LOGVEC) + (p >> logq);
-            if (j >= weff) continue;
+        const int lane = tid & 63;
+        const int g = lane >> 2, q = lane & 3;
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int nwv = nt >> 6;
+        const int rounds = (NB + 15) >> 4;
+        uint32_t maxstep = 0;
+        for (int j = wv; j < weff; j += nwv) {
             const double* a = coeffs + (row0 + (size_t)j) * 4;
             const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
-            const int v0 = blk * 32;
-            const int cnt = min(32, L - v0);
-            uint16_t* dst = lut + (row0 + (size_t)j) * (size_t)L + v0;
-            uint32_t lo = 0, hi = 0, prev = 0, base = 0;
-            for (int g = 0; g < cnt; g += 8) {
-                const int n = min(8, cnt - g);
+            uint16_t* dst = lut + (row0 + (size_t)j) * (size_t)L;
+            const int p = ((j & (VEC - 1)) << logq) + (j >> LOGVEC);
+            for (int r = 0; r < rounds; ++r) {
+                const int blk = (r << 4) + g;
+                const int v0 = (blk << 5) + (q << 3);
+                const int n = max(0, min(8, L - v0));
                 uint32_t e[8];
 #pragma unroll
+                for (int k = 0; k < 8; ++k) e[k] = k < n ? lut_entry(a0, a1, a2, a3, v0 + k, lim) : 0u;
+                if (write_lut && n > 0) store_lut8(dst + v0, e, n, lut_vec);
+                // Step i of a block (bit i of the planes) is entry i+1 minus
+                // entry i; a step that leaves the block or the row is 0.
+                const uint32_t nxt = (uint32_t)__shfl_down((int)e[0], 1, 64);
+                uint32_t lo8 = 0, hi8 = 0;
+#pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    e[k] = k < n ? lut_entry(a0, a1, a2, a3, v0 + g + k, lim) : 0u;
-                    const int i = g + k;  // entry index within the block
-                    if (k < n) {
-                        if (i == 0) {
-                            base = e[k];
-                        } else {
-                            const uint32_t step = e[k] - prev;  // wraps when negative
-                            bad |= step > 3u;
-                            lo |= (step & 1u) << (i - 1);
-                            hi |= ((step >> 1) & 1u) << (i - 1);
-                        }
-                        prev = e[k];
-                    }
+                    const bool has = k < 7 ? k + 1 < n : (q < 3 && n == 8 && v0 + 8 < L);
+                    const uint32_t step = has ? (k < 7 ? e[k + 1] : nxt) - e[k] : 0u;
+                    maxstep = max(maxstep, step);  // wraps high when negative
+                    lo8 |= (step & 1u) << k;
+                    hi8 |= ((step >> 1) & 1u) << k;
                 }
-                if (write_lut) store_lut8(dst + g, e, n, lut_vec);
+                uint32_t lo = lo8 << (q << 3), hi = hi8 << (q << 3);
+                lo |= (uint32_t)__shfl_xor((int)lo, 1, 64);
+                hi |= (uint32_t)__shfl_xor((int)hi, 1, 64);
+                lo |= (uint32_t)__shfl_xor((int)lo, 2, 64);
+                hi |= (uint32_t)__shfl_xor((int)hi, 2, 64);
+                if (q == 0 && blk < NB) {
+                    u32x2 pl;
+                    pl.x = lo;
+                    pl.y = hi;
+                    planes[blk * W + p] = pl;
+                    bases[blk * W + p] = (uint16_t)e[0];
+                }
             }
-            u32x2 pl;
-            pl.x = lo;
-            pl.y = hi;
-            planes[blk * W + p] = pl;
-            bases[blk * W + p] = (uint16_t)base;
         }
+        bad = maxstep > 3u ? 1 : 0;
         bad = __syncthreads_or(bad);
     }
     return bad;

@@ -28,6 +28,8 @@ SPECS = [
     (2, 0, 50, 1024, "quad", 0, False),         # LUT only, no lines
     (1, 90, 100, 1024, "quad", 1, False),       # 2-byte aligned image
     (1, 9000, 64, 1024, "quad", 0, False),      # lines split into chunks
+    (2, 120, 90, 700, "quad", 0, False),        # packed: 22 blocks, L % 8 != 0
+    (1, 50, 40, 513, "quad", 0, False),         # packed: last block holds one level
 ]
 
 
