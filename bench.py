@@ -284,7 +284,7 @@ def bench_serve(args, torch, rc, dev):
         "plain_p99_latency_ms": round(percentile(plain_lat, 99) * 1e3, 2),
         "pinned_h2d_gb_s": round(h2d_gbs, 1), "pinned_d2h_gb_s": round(d2h_gbs, 1),
         "pcie_bound_gpix_s": round(min(h2d_gbs, d2h_gbs) / 2, 2),
-        "quanta": info["quanta"], "tiles": info["tiles"],
+        "quanta": info["quanta"], "tiles": info["tiles"], "direct_out_jobs": info["direct_out"],
         "all_ok": ok, "bit_exact_oracle_sample": exact,
         "oracle_sample_jobs": sorted(int(i) for i in verify), "setup_s": round(setup_s, 1),
     }

@@ -238,9 +238,12 @@ typedef struct {
 /*
  * A job in host memory. Layouts as for rc_lut_build / rc_correct. Use pinned
  * memory (rc_host_alloc) for full-speed, asynchronous copies; pageable
- * buffers work but make the scheduler wait on each copy. The caller owns the
- * buffers and must keep them valid, and not modify dn/coeffs, until
- * rc_server_wait or rc_server_poll reports the job finished.
+ * buffers work but make the scheduler wait on each copy. When `out` is one
+ * pinned allocation the device can address, the kernel writes the corrected
+ * image into it directly (no device copy of the output, no copy back). The
+ * caller owns the buffers and must keep them valid, and not modify dn/coeffs
+ * or read out, until rc_server_wait or rc_server_poll reports the job
+ * finished.
  */
 typedef struct {
     const double* coeffs;  /* host, [bands][detectors][4] */
@@ -272,7 +275,7 @@ typedef struct {
     uint64_t arena_bytes, arena_used;
     int32_t pending, active;   /* jobs waiting for admission / admitted */
     int32_t waiters;           /* threads blocked in rc_server_wait */
-    int32_t reserved;
+    int32_t direct_out;        /* submitted jobs whose output the kernel writes to host memory */
 } rc_server_stats;
 
 /* Creates a server on the current device (arena, streams, scheduler thread).

@@ -109,7 +109,7 @@ class ServerStats(ctypes.Structure):
                 ("pixels", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
                 ("arena_used", ctypes.c_uint64), ("pending", ctypes.c_int32),
                 ("active", ctypes.c_int32), ("waiters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("direct_out", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -9,8 +9,11 @@
 // has arrived, from all admitted jobs, into quanta of the persistent fused
 // kernel on the compute stream. When the last tile of a piece has been
 // issued, the piece is copied back on a device-to-host stream behind that
-// quantum. Copies in both directions overlap each other and the kernels, and
-// a job arriving while others run joins the next quantum.
+// quantum. When the output buffer is pinned host memory that the device can
+// address (rc_host_alloc), the kernel writes the corrected lines straight to
+// it instead: the copy back would otherwise run as a copy kernel competing
+// with the quanta for the CUs. Copies and kernels overlap, and a job arriving
+// while others run joins the next quantum.
 //
 // Every kernel launched here terminates on its own (no kernel waits on host
 // memory); the scheduler polls HIP events from the host.
@@ -111,6 +114,7 @@ struct Job {
     int64_t pixels = 0, rows = 0, lut_n = 0;
     size_t off = 0, bytes = 0;  // arena region
     size_t off_coeffs = 0, off_lut = 0, off_dn = 0, off_out = 0;
+    uint16_t* direct_out = nullptr;  // device address of the pinned host output, or null
     BatchReq req{};             // device pointers filled at admission
     std::vector<Piece> pieces;
     size_t next_arrival = 0;    // first piece not yet seen arrived
@@ -189,8 +193,10 @@ void put_event(rc_server* s, hipEvent_t& e) {
     e = nullptr;
 }
 
-// Device bytes a job occupies: coefficients, LUT, input and output images.
-size_t job_bytes(const rc_host_job& j, size_t* off_lut, size_t* off_dn, size_t* off_out) {
+// Device bytes a job occupies: coefficients, LUT, input image and, unless the
+// kernel writes the host output directly, the output image.
+size_t job_bytes(const rc_host_job& j, bool direct_out, size_t* off_lut, size_t* off_dn,
+                 size_t* off_out) {
     const size_t rows = (size_t)j.bands * (size_t)j.detectors;
     const size_t px = rows * (size_t)j.lines;
     size_t o = round_up(rows * 32, 256);
@@ -199,8 +205,23 @@ size_t job_bytes(const rc_host_job& j, size_t* off_lut, size_t* off_dn, size_t* 
     *off_dn = o;
     o += round_up(px * 2, 256);
     *off_out = o;
-    o += round_up(px * 2, 256);
+    if (!direct_out) o += round_up(px * 2, 256);
     return o;
+}
+
+// Device address of [p, p + bytes) if it is one pinned host allocation the
+// device maps contiguously, else null (HIP's error state is cleared).
+uint16_t* mapped_host(const void* p, size_t bytes) {
+    void* d0 = nullptr;
+    void* d1 = nullptr;
+    const char* last = (const char*)p + (bytes - 1);
+    if (!p || bytes == 0 || hipHostGetDevicePointer(&d0, const_cast<void*>(p), 0) != hipSuccess ||
+        hipHostGetDevicePointer(&d1, (void*)last, 0) != hipSuccess || !d0 ||
+        (const char*)d1 - (const char*)d0 != (ptrdiff_t)(bytes - 1)) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return (uint16_t*)d0;
 }
 
 rc_status validate_job(const rc_host_job& j) {
@@ -242,13 +263,13 @@ hipError_t admit(rc_server* s, const std::shared_ptr<Job>& jp) {
     const rc_host_job& h = j.host;
     unsigned char* base = s->arena_base + j.off;
     j.off_coeffs = 0;
-    job_bytes(h, &j.off_lut, &j.off_dn, &j.off_out);
+    job_bytes(h, j.direct_out != nullptr, &j.off_lut, &j.off_dn, &j.off_out);
     BatchReq& q = j.req;
     std::memset(&q, 0, sizeof q);
     q.coeffs = (const double*)(base + j.off_coeffs);
     q.lut = (uint16_t*)(base + j.off_lut);
     q.dn = (const uint16_t*)(base + j.off_dn);
-    q.out = (uint16_t*)(base + j.off_out);
+    q.out = j.direct_out ? j.direct_out : (uint16_t*)(base + j.off_out);
     q.lines = h.lines;
     q.detectors = h.detectors;
     q.bands = h.bands;
@@ -317,9 +338,17 @@ hipError_t admit(rc_server* s, const std::shared_ptr<Job>& jp) {
     return hipSuccess;
 }
 
-// Enqueues the copy back of a piece behind the quantum event `after`.
+// Enqueues the copy back of a piece behind the quantum event `after`. With a
+// direct output the piece is done when the quantum is: its event is recorded
+// on the compute stream right behind it.
 hipError_t finish_piece(rc_server* s, Job& j, Piece& pc, hipEvent_t after) {
     const rc_host_job& h = j.host;
+    if (j.direct_out) {
+        pc.ev_out = get_event(s);
+        if (!pc.ev_out) return hipErrorOutOfMemory;
+        pc.state = kIssued;
+        return hipEventRecord(pc.ev_out, s->s_comp);
+    }
     hipError_t e = hipStreamWaitEvent(s->s_out, after, 0);
     if (e != hipSuccess) return e;
     if (pc.n1 > pc.n0) {
@@ -683,8 +712,9 @@ rc_status rc_server_submit(rc_server* s, const rc_host_job* j, uint64_t* job_id)
     jp->rows = (int64_t)j->bands * j->detectors;
     jp->pixels = jp->rows * j->lines;
     jp->lut_n = jp->rows * j->levels;
+    if (jp->pixels > 0) jp->direct_out = mapped_host(j->out, (size_t)jp->pixels * 2);
     size_t a, b, c;
-    jp->bytes = job_bytes(*j, &a, &b, &c);
+    jp->bytes = job_bytes(*j, jp->direct_out != nullptr, &a, &b, &c);
     jp->submit_s = now_s();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return RC_ECLOSED;
@@ -694,6 +724,7 @@ rc_status rc_server_submit(rc_server* s, const rc_host_job* j, uint64_t* job_id)
     s->jobs[jp->id] = jp;
     s->pending.push_back(jp);
     s->stats.submitted += 1;
+    if (jp->direct_out) s->stats.direct_out += 1;
     *job_id = jp->id;
     s->cv_work.notify_one();
     return RC_OK;
@@ -747,7 +778,6 @@ rc_status rc_server_info(rc_server* s, rc_server_stats* st) {
     st->pending = (int32_t)s->pending.size();
     st->active = (int32_t)s->active.size();
     st->waiters = s->waiters;
-    st->reserved = 0;
     return RC_OK;
 }
 

@@ -58,11 +58,14 @@ def job_bytes(spec):
     return r(32 * B * D) + r(2 * B * D * L) + 2 * r(2 * B * N * D)
 
 
-def run(srv, jobs, idx):
+def run(srv, jobs, idx, pageable=()):
+    """Pinned outputs are written by the kernel directly; outputs in `pageable`
+    (ordinary numpy memory) go through the device-to-host copy path."""
     outs = {}
     for i in idx:
         c, d, wl, w = jobs[i]
-        outs[i] = (rc.pinned_empty(w.shape, np.uint16), rc.pinned_empty(wl.shape, np.uint16))
+        img = np.empty(w.shape, np.uint16) if i in pageable else rc.pinned_empty(w.shape, np.uint16)
+        outs[i] = (img, rc.pinned_empty(wl.shape, np.uint16))
     ids = {i: srv.submit(jobs[i][0], jobs[i][1], outs[i][0], SPECS[i][3], lut=outs[i][1])
            for i in idx}
     return outs, ids
@@ -84,7 +87,7 @@ def test_alone_equals_mix_equals_oracle(jobs):
     # small pieces and quanta so that tiles of different jobs share launches.
     arena = 3 * max(job_bytes(s) for s in SPECS)
     srv = rc.Server(arena_bytes=arena, max_jobs=4, piece_pixels=1 << 16, max_quantum_tiles=64)
-    outs, ids = run(srv, jobs, range(len(SPECS)))
+    outs, ids = run(srv, jobs, range(len(SPECS)), pageable={i for i in range(len(SPECS)) if i % 2})
     for i in range(len(SPECS)):
         st = srv.wait(ids[i])
         assert st["status"] == rc.RC_OK, SPECS[i]
@@ -93,6 +96,8 @@ def test_alone_equals_mix_equals_oracle(jobs):
         assert np.array_equal(outs[i][1], alone[i][1]), f"mix LUT != alone {SPECS[i]}"
     info = srv.info()
     assert info["completed"] == len(SPECS) and info["quanta"] > 1 and info["arena_used"] == 0
+    # Pinned outputs of jobs with pixels are written directly; pageable ones are copied.
+    assert info["direct_out"] == sum(1 for i, sp in enumerate(SPECS) if i % 2 == 0 and sp[1] > 0)
     srv.close()
 
 
