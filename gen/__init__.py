@@ -74,6 +74,9 @@ def _load():
                                    ctypes.c_double, P(ctypes.c_double), P(i64), P(i32),
                                    P(i32), P(i32)]
     lib.gen_serve_jobs.restype = None
+    lib.gen_calib.argtypes = [u64, i32, i64, i32, i32, i32, i32, P(ctypes.c_double),
+                              P(ctypes.c_double)]
+    lib.gen_calib.restype = None
     _lib = lib
     return lib
 
@@ -106,6 +109,46 @@ def dn(seed, cfg, req, kind, bands, lines, detectors, n0=0, nlines=None, out=Non
     _load().gen_dn(seed, cfg, req, kind, bands, lines, detectors, n0, nlines,
                    _ptr(out, ctypes.c_uint16), threads)
     return out
+
+
+def calib(seed, cfg, req, bands, points, detectors, levels):
+    """Calibration acquisitions: x [bands, points, detectors] (detector
+    responses on `points` flat-field lines) and y [bands, points] (the lines'
+    reference levels), float64."""
+    x = np.empty((bands, points, detectors), dtype=np.float64)
+    y = np.empty((bands, points), dtype=np.float64)
+    _load().gen_calib(seed, cfg, req, bands, points, detectors, levels,
+                      _ptr(x, ctypes.c_double), _ptr(y, ctypes.c_double))
+    return x, y
+
+
+@dataclass
+class Calib:
+    """A least-squares calibration fit: `points` calibration lines of
+    `detectors` detectors per band, polynomial order `order`."""
+    name: str
+    seed: int
+    cfg: int
+    bands: int
+    points: int
+    detectors: int
+    levels: int
+    order: int
+
+    def data(self):
+        return calib(self.seed, self.cfg, 0, self.bands, self.points, self.detectors, self.levels)
+
+
+def fit_workload(i, seed=None):
+    """Fit workloads: 0 = the paper's data shape (one band, 6 calibration
+    lines of 6000 pixels), order 2; 1 = the calibration of the 4-band,
+    12000-detector scene, 6 lines, order 2."""
+    s = BASE_SEED + 5 if seed is None else seed
+    if i == 0:
+        return Calib("1x6x6000_order2", s, 5, 1, 6, 6000, 1024, 2)
+    if i == 1:
+        return Calib("4x6x12000_order2", s, 6, 4, 6, 12000, 1024, 2)
+    raise ValueError(f"no fit workload {i}")
 
 
 @dataclass

@@ -1,7 +1,8 @@
 // Seeded synthetic input generators for the LUT-correction workloads.
 //
 // This module only draws inputs: calibration coefficients, digital-number
-// (DN) images, batch request shapes and serving job traces. It holds none of
+// (DN) images, calibration acquisitions for the least-squares fit, batch
+// request shapes and serving job traces. It holds none of
 // the LUT or correction arithmetic. Both the GPU library's tests and the CPU
 // oracle receive the same host buffers produced here.
 //
@@ -31,6 +32,7 @@ enum Role : uint64_t {
     kRolePhase = 5,
     kRoleDims = 6,
     kRoleArrival = 7,
+    kRoleCalib = 8,
 };
 
 inline uint64_t mix64(uint64_t z) {
@@ -235,6 +237,37 @@ void gen_serve_jobs(uint64_t seed, int32_t cfg, int32_t n, double qps, double mp
         const double nl = std::round(pix / ((double)bands[r] * (double)detectors[r]));
         lines[r] = nl < 1.0 ? 1 : (int64_t)nl;
         depth[r] = below(draw(k, 3), 2) ? 12 : 10;
+    }
+}
+
+// Calibration acquisitions for the least-squares fit: per band, `points`
+// flat-field lines at reference levels y_i = (i + 1) / (points + 1) * (L - 1),
+// and each detector's response to them,
+//   x[b][i][d] = o + g * y_i + c * y_i^2 + e,
+// with per-detector o ~ N(0, L / 128), g ~ U(0.9, 1.1), c ~ N(0, 0.01 / L)
+// and per-point noise e ~ N(0, 0.5) (an average over frames). y is
+// [bands][points], x is [bands][points][detectors].
+void gen_calib(uint64_t seed, int32_t cfg, int64_t req, int32_t bands, int32_t points,
+               int32_t detectors, int32_t levels, double* x, double* y) {
+    const double top = (double)(levels - 1);
+    for (int32_t b = 0; b < bands; ++b) {
+        const uint64_t key = stream_key(seed, (uint64_t)cfg, (uint64_t)req, (uint64_t)b,
+                                        kRoleCalib);
+        for (int32_t i = 0; i < points; ++i)
+            y[(size_t)b * (size_t)points + (size_t)i] =
+                (double)(i + 1) / (double)(points + 1) * top;
+        for (int32_t d = 0; d < detectors; ++d) {
+            const uint64_t base = (uint64_t)d * (uint64_t)(points + 4);
+            const double o = (double)levels / 128.0 * normal(key, base + 0);
+            const double g = 0.9 + 0.2 * unif(draw(key, 2 * (base + 1)));
+            const double c = 0.01 / (double)levels * normal(key, base + 2);
+            for (int32_t i = 0; i < points; ++i) {
+                const double yi = y[(size_t)b * (size_t)points + (size_t)i];
+                const double e = 0.5 * normal(key, base + 4 + (uint64_t)i);
+                x[((size_t)b * (size_t)points + (size_t)i) * (size_t)detectors + (size_t)d] =
+                    o + g * yi + c * yi * yi + e;
+            }
+        }
     }
 }
 

@@ -33,6 +33,8 @@ def _load(path=None):
     lib.oracle_correct.restype = None
     lib.oracle_pixel.argtypes = [f64p, u16p, i64, i32, i32, i32, u16p]
     lib.oracle_pixel.restype = None
+    lib.oracle_fit.argtypes = [f64p, f64p, i32, i32, i32, i32, f64p]
+    lib.oracle_fit.restype = None
     if path is None:
         _lib = lib
     return lib
@@ -90,6 +92,19 @@ class Oracle:
         if out is None:
             out = np.empty_like(dn)
         self.lib.oracle_pixel(_f64(coeffs), _u16(dn), N, D, B, int(levels), _u16(out))
+        return out
+
+
+    def fit(self, x, y, order, out=None):
+        """Least-squares fit. x: float64 [B, n, D] (detector values on n
+        calibration lines), y: float64 [B, n] (targets) -> float64 [B, D, 4]."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        B, n, D = x.shape
+        assert y.shape == (B, n)
+        if out is None:
+            out = np.empty((B, D, 4), dtype=np.float64)
+        self.lib.oracle_fit(_f64(x), _f64(y), B, n, D, int(order), _f64(out))
         return out
 
 

@@ -88,4 +88,87 @@ void oracle_pixel(const double* coeffs, const uint16_t* dn, int64_t lines,
     }
 }
 
+// Case study 2 of the paper (§III.B): the least-squares polynomial fit,
+// applied per detector to its calibration points. Setting the first
+// derivatives of the squared error to zero gives the normal equations
+// A a = B with A[j][k] = sum_i x_i^(j+k) and B[j] = sum_i x_i^j y_i (the
+// printed derivative lacks the factor -2 x_i^j and the printed A starts with
+// 1 where sum_i x_i^0 = n belongs; both are read as the standard equations).
+// The paper solves them as a = A^-1 B; A^-1 comes from Gauss-Jordan
+// elimination of [A | I] with partial pivoting.
+void oracle_fit(const double* x, const double* y, int32_t bands, int32_t points,
+                int32_t detectors, int32_t order, double* coeffs) {
+    const int m = order;
+    const int w = 2 * (m + 1);  // columns of [A | I]
+    for (int32_t b = 0; b < bands; ++b) {
+        for (int32_t d = 0; d < detectors; ++d) {
+            // Power sums S[k] = sum_i x_i^k (k <= 2m) and T[j] = sum_i x_i^j y_i.
+            double S[7] = {0, 0, 0, 0, 0, 0, 0};
+            double T[4] = {0, 0, 0, 0};
+            for (int32_t i = 0; i < points; ++i) {
+                const double xi = x[((size_t)b * (size_t)points + (size_t)i) * (size_t)detectors
+                                    + (size_t)d];
+                const double yi = y[(size_t)b * (size_t)points + (size_t)i];
+                double p = 1.0;  // x_i^k
+                for (int k = 0; k <= 2 * m; ++k) {
+                    S[k] = S[k] + p;
+                    if (k <= m) T[k] = T[k] + p * yi;
+                    p = p * xi;
+                }
+            }
+            // [A | I]
+            double M[4][8];
+            for (int j = 0; j <= m; ++j) {
+                for (int k = 0; k <= m; ++k) {
+                    M[j][k] = S[j + k];
+                    M[j][m + 1 + k] = j == k ? 1.0 : 0.0;
+                }
+            }
+            bool singular = false;
+            for (int c = 0; c <= m; ++c) {
+                // Pivot: the first row (from c down) of largest magnitude in column c.
+                int pr = c;
+                double best = std::fabs(M[c][c]);
+                for (int r = c + 1; r <= m; ++r) {
+                    if (std::fabs(M[r][c]) > best) {
+                        best = std::fabs(M[r][c]);
+                        pr = r;
+                    }
+                }
+                if (!(best > 0.0)) {
+                    singular = true;
+                    break;
+                }
+                if (pr != c) {
+                    for (int k = 0; k < w; ++k) {
+                        const double t = M[c][k];
+                        M[c][k] = M[pr][k];
+                        M[pr][k] = t;
+                    }
+                }
+                const double piv = M[c][c];
+                for (int k = 0; k < w; ++k) M[c][k] = M[c][k] / piv;
+                for (int r = 0; r <= m; ++r) {
+                    if (r == c) continue;
+                    const double f = M[r][c];
+                    for (int k = 0; k < w; ++k) M[r][k] = M[r][k] - f * M[c][k];
+                }
+            }
+            double* a = coeffs + ((size_t)b * (size_t)detectors + (size_t)d) * 4;
+            for (int j = 0; j < 4; ++j) {
+                if (singular) {
+                    a[j] = std::nan("");
+                } else if (j > m) {
+                    a[j] = 0.0;
+                } else {
+                    // a_j = sum_k (A^-1)[j][k] * B[k]
+                    double s = 0.0;
+                    for (int k = 0; k <= m; ++k) s = s + M[j][m + 1 + k] * T[k];
+                    a[j] = s;
+                }
+            }
+        }
+    }
+}
+
 }  // extern "C"

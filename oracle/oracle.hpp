@@ -19,7 +19,17 @@
 //   Correction (per pixel gather), band-sequential push-broom image [B][N][D]:
 //     out[b][n][d] = lut[b][d][min(dn[b][n][d], L-1)]
 //
-// Parity pins (independent of this file) live in tests/test_oracle_pins.py.
+//   Least-squares calibration fit (§III.B, case study 2), per band b and detector d,
+//   over n points (x_i, y_i) = (x[b][i][d], y[b][i]), i < n, polynomial order m <= 3:
+//     normal equations  A a = B,  A[j][k] = sum_i x_i^(j+k)  (A[0][0] = n),
+//                                 B[j]    = sum_i x_i^j * y_i,   j, k = 0..m
+//     solved as a = A^-1 B, A^-1 by Gauss-Jordan elimination with partial pivoting.
+//   Powers by repeated multiplication, sums over i in increasing order, binary64,
+//   no FMA. coeffs[b][d][0..3] = a_0..a_m, then +0.0 above the order; a singular
+//   system (no nonzero pivot) gives NaN in all four.
+//
+// Parity pins (independent of this file) live in tests/test_oracle_pins.py and
+// tests/test_oracle_fit_pins.py.
 #pragma once
 #include <stdint.h>
 
@@ -46,6 +56,11 @@ void oracle_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines,
 void oracle_pixel(const double* coeffs, const uint16_t* dn, int64_t lines,
                   int32_t detectors, int32_t bands, int32_t levels,
                   uint16_t* out);
+
+// Least-squares fit (definition above). x is [bands][points][detectors],
+// y is [bands][points], coeffs is [bands][detectors][4]; 0 <= order <= 3.
+void oracle_fit(const double* x, const double* y, int32_t bands, int32_t points,
+                int32_t detectors, int32_t order, double* coeffs);
 
 #ifdef __cplusplus
 }

@@ -55,3 +55,16 @@ def test_batch_and_serve_shapes():
     assert abs(len(t) / t[-1] - 150) < 40
     for _, j in trace:
         assert 1024 <= j.detectors <= 12000 and 1 <= j.bands <= 4
+
+
+def test_calib_is_deterministic_and_shaped():
+    x1, y1 = gen.calib(gen.BASE_SEED, 5, 0, 2, 6, 100, 1024)
+    x2, y2 = gen.calib(gen.BASE_SEED, 5, 0, 2, 6, 100, 1024)
+    assert x1.shape == (2, 6, 100) and y1.shape == (2, 6)
+    assert np.array_equal(x1, x2) and np.array_equal(y1, y2)
+    # Reference levels evenly inside (0, L-1); responses rise with the level.
+    assert np.allclose(y1[0], np.arange(1, 7) / 7 * 1023)
+    assert (np.diff(x1, axis=1) > 0).mean() > 0.99
+    # A detector's data do not depend on how many detectors are drawn.
+    x3, _ = gen.calib(gen.BASE_SEED, 5, 0, 2, 6, 40, 1024)
+    assert np.array_equal(x3, x1[:, :, :40])

@@ -10,6 +10,7 @@ import pytest
 import oracle
 from oracle import build as obuild
 import pins
+import pins_fit
 
 SRC = os.path.join(os.path.dirname(obuild.__file__), "oracle.cpp")
 
@@ -40,6 +41,25 @@ MUTANTS = {
 }
 
 
+# Plausible mistakes in the least-squares fit (§III.B), two of them the
+# paper's own misprints taken literally.
+MUTANTS_FIT = {
+    "fit_a00_is_one": [("M[j][k] = S[j + k];", "M[j][k] = j + k == 0 ? 1.0 : S[j + k];")],
+    "fit_b_without_xj": [("if (k <= m) T[k] = T[k] + p * yi;", "if (k <= m) T[k] = T[k] + yi;")],
+    "fit_power_off_by_one": [("M[j][k] = S[j + k];", "M[j][k] = S[j + k < 2 * m ? j + k + 1 : j + k];")],
+    "fit_pivot_row_not_scaled": [("for (int k = 0; k < w; ++k) M[c][k] = M[c][k] / piv;", "")],
+    "fit_drops_first_point": [("for (int32_t i = 0; i < points; ++i) {\n                const double xi",
+                               "for (int32_t i = 1; i < points; ++i) {\n                const double xi")],
+    "fit_target_ignores_band": [("const double yi = y[(size_t)b * (size_t)points + (size_t)i];",
+                                 "const double yi = y[(size_t)i];")],
+    "fit_padding_one": [("a[j] = 0.0;", "a[j] = 1.0;")],
+    "fit_x_stride_swap": [("const double xi = x[((size_t)b * (size_t)points + (size_t)i) * (size_t)detectors\n"
+                           "                                    + (size_t)d];",
+                           "const double xi = x[((size_t)b * (size_t)detectors + (size_t)d) * (size_t)points\n"
+                           "                                    + (size_t)i];")],
+}
+
+
 def _saturation_pin(o):
     L = 1024
     lut = (np.arange(2 * L, dtype=np.int64).reshape(1, 2, L) % 997).astype(np.uint16)
@@ -67,3 +87,23 @@ def test_mutant_is_caught(name, tmp_path):
             caught.append(pin.__name__)
             break
     assert caught, f"mutant {name} passed every pin"
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS_FIT))
+def test_fit_mutant_is_caught(name, tmp_path):
+    src = open(SRC).read()
+    for old, new in MUTANTS_FIT[name]:
+        assert src.count(old) == 1, f"mutation site not unique for {name}: {old!r}"
+        src = src.replace(old, new)
+    path = tmp_path / "oracle_mutant.cpp"
+    path.write_text(src)
+    lib = obuild.build(src=str(path), out=str(tmp_path / "liboracle_mutant.so"))
+    o = oracle.Oracle(lib)
+    caught = []
+    for pin in pins_fit.ALL_FIT_PINS:
+        try:
+            pin(o)
+        except AssertionError:
+            caught.append(pin.__name__)
+            break
+    assert caught, f"mutant {name} passed every fit pin"
