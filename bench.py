@@ -36,6 +36,7 @@ def parse():
                     help="minimum CPU time spent timing the oracle")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-request batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-fit", action="store_true", help="skip the calibration-fit leg")
     ap.add_argument("--serve-jobs", type=int, default=300)
     ap.add_argument("--serve-qps", type=float, default=150.0)
     ap.add_argument("--batch-requests", type=int, default=256)
@@ -142,6 +143,51 @@ def bench_batch(args, torch, rc, dev):
         "bit_exact_oracle_sample": oracle_ok, "oracle_sample_requests": [int(i) for i in sample],
         "setup_s": round(gen_s, 1),
     }
+
+
+def bench_fit(args, torch, rc, dev):
+    """Least-squares calibration fit (the paper's case study 2, the step that
+    produces the coefficients): the paper's data shape and the calibration of
+    the benchmark scene, each timed on the launch stream and checked bit for
+    bit against the oracle, which is timed beside it."""
+    import gen
+    import oracle
+    o = oracle.get()
+    stream = torch.cuda.Stream(device=dev)
+    res = []
+    for w in (0, 1):
+        c = gen.fit_workload(w)
+        x, y = c.data()
+        xt, yt = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+        out = torch.empty((c.bands, c.detectors, 4), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            rc.rc_fit(xt, yt, c.bands, c.points, c.detectors, c.order, out, stream)
+        reps = 200
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            rc.rc_fit(xt, yt, c.bands, c.points, c.detectors, c.order, out, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        c0, k = time.perf_counter(), 0
+        while True:
+            want = o.fit(x, y, c.order)
+            k += 1
+            if time.perf_counter() - c0 > 0.5:
+                break
+        cpu_us = (time.perf_counter() - c0) * 1e6 / k
+        got = out.cpu().numpy()
+        exact = bool(np.array_equal(got.view(np.uint64), want.view(np.uint64)))
+        nbytes = x.nbytes + y.nbytes + got.nbytes
+        res.append({"workload": c.name, "bands": c.bands, "points": c.points,
+                    "detectors": c.detectors, "order": c.order,
+                    "fit_us": round(us, 2), "detectors_per_s": round(c.bands * c.detectors / (us * 1e-6), 1),
+                    "bytes": nbytes, "gb_s": round(nbytes / (us * 1e-6) / 1e9, 1),
+                    "frac_hbm": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
+                    "oracle_us": round(cpu_us, 1), "oracle_cores": 1, "bit_exact": exact})
+    return res
 
 
 def percentile(xs, q):
@@ -422,6 +468,8 @@ def main():
             got_lut = lut_t.cpu().numpy().view(np.uint16)
             bit_exact = bool(np.array_equal(got, want) and np.array_equal(got_lut, want_lut))
 
+    fit_res = None if args.no_fit else bench_fit(args, torch, rc, dev)
+
     batch_res = None
     del dn_t, out_t, lut_t, c_t
     torch.cuda.empty_cache()
@@ -466,6 +514,7 @@ def main():
                              "min": round(min(build_ms), 4)},
             "lut_build_gb_s": round(build_bytes / (statistics.mean(build_ms) * 1e-3) / 1e9, 1),
         },
+        "fit": fit_res,
         "batch": batch_res,
         "serve": serve_res,
         "device": {"name": props.name, "cus": props.multi_processor_count,

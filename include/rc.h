@@ -128,6 +128,39 @@ rc_status rc_correct_plan(const uint16_t* dn, const uint16_t* lut, int64_t lines
                           int32_t detectors, int32_t bands, int32_t levels, uint16_t* out,
                           const rc_plan* plan, hipStream_t stream);
 
+/* ---- least-squares calibration fit ---------------------------------------------------- */
+
+/*
+ * The calibration step upstream of rc_lut_build: case study 2 of the paper
+ * (§III.B, least-squares curve fit of any order), applied per band b and
+ * detector d to that detector's responses on `points` calibration lines.
+ * Fits f(x) = a0 + a1 x + ... + a_m x^m, m = order, to the pairs
+ * (x[b][i][d], y[b][i]), i < points, minimising sum_i (y_i - f(x_i))^2 through
+ * the normal equations A a = B, A[j][k] = sum_i x_i^(j+k) (A[0][0] = points),
+ * B[j] = sum_i x_i^j y_i, solved as a = A^-1 B with A^-1 from Gauss-Jordan
+ * elimination with partial pivoting. Binary64, no fused multiply-add, powers
+ * by repeated multiplication and sums in point order: every detector's
+ * result is a fixed sequence of IEEE operations (bit-identical to a CPU that
+ * follows the same steps). The normal equations are ill-conditioned for
+ * large x and high orders (cond(A) ~ 1e12 for order 2 over a 10-bit range);
+ * the fit is the paper's, not a re-scaled one.
+ *
+ *   x       device, [bands][points][detectors] binary64 (detector responses)
+ *   y       device, [bands][points] binary64 (reference level of each line)
+ *   coeffs  device, [bands][detectors][4] binary64, written: a0..a_m, then +0.0
+ *           above the order (the layout rc_lut_build reads); all four NaN when
+ *           elimination meets no nonzero pivot (e.g. every x_i equal, order >= 1)
+ *   order   0..3;  points >= order + 1
+ *
+ * The caller owns all buffers; nothing is allocated; one kernel is enqueued on
+ * `stream`. RC_EINVAL (nothing enqueued) for order outside 0..3, points <
+ * order + 1, negative sizes, null or not 8-byte-aligned pointers when there
+ * is work, or coeffs overlapping x or y. Zero bands or detectors: RC_OK, no
+ * work.
+ */
+rc_status rc_fit(const double* x, const double* y, int32_t bands, int32_t points,
+                 int32_t detectors, int32_t order, double* coeffs, hipStream_t stream);
+
 /* ---- autotuner and plan cache --------------------------------------------------------- */
 
 /*

@@ -4,10 +4,10 @@ Argument marshalling only. Every step runs in the HIP kernels of librc.so;
 PyTorch provides device memory (tensors) and streams. There is no CPU
 fallback: importing this package fails if the library has not been built.
 
-Functions named like the C ABI (``rc_lut_build``, ``rc_correct``,
+Functions named like the C ABI (``rc_fit``, ``rc_lut_build``, ``rc_correct``,
 ``rc_correct_plan``, ``rc_plan_for``) take device tensors or raw device
-pointers (ints) plus the same sizes as the C functions. ``lut_build`` and
-``correct`` are shape-checked conveniences on top of them.
+pointers (ints) plus the same sizes as the C functions. ``fit``,
+``lut_build`` and ``correct`` are shape-checked conveniences on top of them.
 
 uint16 data is carried in torch.int16 (or torch.uint16) tensors: only the
 bits matter and no arithmetic is done on them in Python.
@@ -121,6 +121,8 @@ _lib.rc_last_hip_error.argtypes = []
 _lib.rc_last_hip_error.restype = _i32
 _lib.rc_lut_build.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_lut_build.restype = ctypes.c_int
+_lib.rc_fit.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp]
+_lib.rc_fit.restype = ctypes.c_int
 _lib.rc_correct.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_correct.restype = ctypes.c_int
 _lib.rc_correct_plan.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, ctypes.POINTER(Plan), _vp]
@@ -202,6 +204,11 @@ def _check(st, where):
 def rc_lut_build(coeffs, bands, detectors, levels, lut, stream=None):
     _check(_lib.rc_lut_build(_ptr(coeffs), bands, detectors, levels, _ptr(lut), _stream(stream)),
            "rc_lut_build")
+
+
+def rc_fit(x, y, bands, points, detectors, order, coeffs, stream=None):
+    _check(_lib.rc_fit(_ptr(x), _ptr(y), bands, points, detectors, order, _ptr(coeffs),
+                       _stream(stream)), "rc_fit")
 
 
 def rc_correct(dn, lut, lines, detectors, bands, levels, out, stream=None):
@@ -403,6 +410,21 @@ def lut_build(coeffs, levels, lut=None, stream=None):
         raise ValueError("lut must be 16-bit [bands, detectors, levels]")
     rc_lut_build(coeffs, B, D, levels, lut, stream)
     return lut
+
+
+def fit(x, y, order, out=None, stream=None):
+    """x: float64 device tensor [B, n, D] (detector responses on n calibration
+    lines), y: [B, n] (the lines' reference levels) -> coefficients [B, D, 4],
+    the layout lut_build takes."""
+    if x.dtype != torch.float64 or y.dtype != torch.float64 or x.dim() != 3 or y.dim() != 2:
+        raise ValueError("x [B, n, D] and y [B, n] must be float64 tensors")
+    B, n, D = x.shape
+    if tuple(y.shape) != (B, n):
+        raise ValueError("y shape does not match x")
+    if out is None:
+        out = torch.empty((B, D, 4), dtype=torch.float64, device=x.device)
+    rc_fit(x.contiguous(), y.contiguous(), B, n, D, order, out, stream)
+    return out
 
 
 def correct(dn, lut, out=None, plan=None, stream=None):

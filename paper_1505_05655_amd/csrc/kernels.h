@@ -31,6 +31,10 @@ struct ApplyParams {
 hipError_t launch_lut_build(const double* coeffs, int64_t rows, int32_t levels, uint16_t* lut,
                             hipStream_t stream);
 
+// Least-squares calibration fit of order 0..3 (arguments validated by rc_fit).
+hipError_t launch_fit(const double* x, const double* y, int32_t bands, int32_t points,
+                      int32_t detectors, int32_t order, double* coeffs, hipStream_t stream);
+
 // Correction with the given plan (already validated).
 hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,
                         hipStream_t stream);

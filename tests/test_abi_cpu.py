@@ -95,6 +95,32 @@ def test_correct_empty_is_noop():
     assert L.rc_correct(None, None, 10, 100, 0, 1024, None, None) == rc.RC_OK
 
 
+@pytest.mark.parametrize("args", [
+    # x, y, bands, points, detectors, order, coeffs
+    (None, FAKE, 1, 6, 4, 2, FAKE * 64),               # NULL x
+    (FAKE, None, 1, 6, 4, 2, FAKE * 64),               # NULL y
+    (FAKE, FAKE * 32, 1, 6, 4, 2, None),               # NULL coeffs
+    (FAKE, FAKE * 32, 1, 6, 4, -1, FAKE * 64),         # order < 0
+    (FAKE, FAKE * 32, 1, 6, 4, 4, FAKE * 64),          # order > 3
+    (FAKE, FAKE * 32, 1, 2, 4, 2, FAKE * 64),          # points < order + 1
+    (FAKE, FAKE * 32, -1, 6, 4, 2, FAKE * 64),         # negative bands
+    (FAKE, FAKE * 32, 1, 6, -4, 2, FAKE * 64),         # negative detectors
+    (FAKE + 4, FAKE * 32, 1, 6, 4, 2, FAKE * 64),      # x not 8-byte aligned
+    (FAKE, FAKE * 32 + 2, 1, 6, 4, 2, FAKE * 64),      # y not 8-byte aligned
+    (FAKE, FAKE * 32, 1, 6, 4, 2, FAKE * 64 + 4),      # coeffs not 8-byte aligned
+    (FAKE, FAKE * 32, 1, 6, 4, 2, FAKE + 64),          # coeffs overlap x
+    (FAKE, FAKE * 32, 1, 6, 4, 2, FAKE * 32 + 8),      # coeffs overlap y
+    (FAKE, FAKE * 32, 1 << 20, 1 << 20, 1 << 20, 1, FAKE * 64),  # sizes overflow
+])
+def test_fit_rejects(args):
+    assert L.rc_fit(*args, None) == rc.RC_EINVAL
+
+
+def test_fit_empty_is_noop():
+    assert L.rc_fit(None, None, 0, 6, 100, 2, None, None) == rc.RC_OK
+    assert L.rc_fit(None, None, 3, 6, 0, 2, None, None) == rc.RC_OK
+
+
 def test_correct_plan_requires_plan():
     assert L.rc_correct_plan(FAKE, FAKE * 64, 4, 4, 1, 1024, FAKE * 128, None, None) == rc.RC_EINVAL
 
