@@ -77,6 +77,8 @@ def _load():
     lib.gen_calib.argtypes = [u64, i32, i64, i32, i32, i32, i32, P(ctypes.c_double),
                               P(ctypes.c_double)]
     lib.gen_calib.restype = None
+    lib.gen_bayer.argtypes = [u64, i32, i64, i32, i32, i32, P(ctypes.c_uint16), i32]
+    lib.gen_bayer.restype = None
     _lib = lib
     return lib
 
@@ -120,6 +122,25 @@ def calib(seed, cfg, req, bands, points, detectors, levels):
     _load().gen_calib(seed, cfg, req, bands, points, detectors, levels,
                       _ptr(x, ctypes.c_double), _ptr(y, ctypes.c_double))
     return x, y
+
+
+def bayer(seed, cfg, req, images, height, width, threads=0):
+    """Raw RGGB Bayer images, uint16 [images, height, width]."""
+    out = np.empty((images, height, width), dtype=np.uint16)
+    _load().gen_bayer(seed, cfg, req, images, height, width, _ptr(out, ctypes.c_uint16), threads)
+    return out
+
+
+def demosaic_workload(i, seed=None):
+    """Demosaicing workloads as (name, seed, cfg, images, height, width):
+    0 = the paper's single 2048 x 2048 16-bit image; 1 = a batch of 16 such
+    images (enough workgroups to fill the GPU)."""
+    s = BASE_SEED + 7 if seed is None else seed
+    if i == 0:
+        return ("1x2048x2048", s, 7, 1, 2048, 2048)
+    if i == 1:
+        return ("16x2048x2048", s, 8, 16, 2048, 2048)
+    raise ValueError(f"no demosaic workload {i}")
 
 
 @dataclass

@@ -1,8 +1,8 @@
 // Seeded synthetic input generators for the LUT-correction workloads.
 //
 // This module only draws inputs: calibration coefficients, digital-number
-// (DN) images, calibration acquisitions for the least-squares fit, batch
-// request shapes and serving job traces. It holds none of
+// (DN) images, calibration acquisitions for the least-squares fit, raw
+// Bayer images, batch request shapes and serving job traces. It holds none of
 // the LUT or correction arithmetic. Both the GPU library's tests and the CPU
 // oracle receive the same host buffers produced here.
 //
@@ -33,6 +33,7 @@ enum Role : uint64_t {
     kRoleDims = 6,
     kRoleArrival = 7,
     kRoleCalib = 8,
+    kRoleBayer = 9,
 };
 
 inline uint64_t mix64(uint64_t z) {
@@ -268,6 +269,38 @@ void gen_calib(uint64_t seed, int32_t cfg, int64_t req, int32_t bands, int32_t p
                     o + g * yi + c * yi * yi + e;
             }
         }
+    }
+}
+
+// Raw 16-bit Bayer images (RGGB) [images][height][width]: a smooth scene per
+// colour channel k (0 = R, 1 = G, 2 = B),
+//   v = 30000 + 20000 sin(2 pi c / 517 + phi_k) cos(2 pi r / 389 + psi_k) + 500 e,
+// e ~ N(0, 1) per pixel, sampled at each pixel for the colour of its filter,
+// rounded and clamped to [0, 65535]; phases drawn per image and channel.
+void gen_bayer(uint64_t seed, int32_t cfg, int64_t req, int32_t images, int32_t height,
+               int32_t width, uint16_t* out, int32_t threads) {
+    for (int32_t k = 0; k < images; ++k) {
+        const uint64_t key = stream_key(seed, (uint64_t)cfg, (uint64_t)req, (uint64_t)k,
+                                        kRoleBayer);
+        double phi[3], psi[3];
+        for (int ch = 0; ch < 3; ++ch) {
+            phi[ch] = kTwoPi * unif(draw(key, (uint64_t)(2 * ch)));
+            psi[ch] = kTwoPi * unif(draw(key, (uint64_t)(2 * ch + 1)));
+        }
+        uint16_t* im = out + (size_t)k * (size_t)height * (size_t)width;
+        parallel_rows(height, threads, [&](int64_t r0, int64_t r1) {
+            for (int64_t r = r0; r < r1; ++r) {
+                for (int32_t c = 0; c < width; ++c) {
+                    const int ch = (r % 2 == 0 && c % 2 == 0) ? 0 : (r % 2 == 1 && c % 2 == 1) ? 2 : 1;
+                    const uint64_t i = 8 + (uint64_t)r * (uint64_t)width + (uint64_t)c;
+                    double v = 30000.0 + 20000.0 * std::sin(kTwoPi * (double)c / 517.0 + phi[ch]) *
+                                             std::cos(kTwoPi * (double)r / 389.0 + psi[ch]) +
+                               500.0 * normal(key, i);
+                    v = std::min(std::max(std::round(v), 0.0), 65535.0);
+                    im[(size_t)r * (size_t)width + (size_t)c] = (uint16_t)v;
+                }
+            }
+        });
     }
 }
 

@@ -35,6 +35,8 @@ def _load(path=None):
     lib.oracle_pixel.restype = None
     lib.oracle_fit.argtypes = [f64p, f64p, i32, i32, i32, i32, f64p]
     lib.oracle_fit.restype = None
+    lib.oracle_demosaic.argtypes = [u16p, i32, i32, i32, u16p]
+    lib.oracle_demosaic.restype = None
     if path is None:
         _lib = lib
     return lib
@@ -105,6 +107,16 @@ class Oracle:
         if out is None:
             out = np.empty((B, D, 4), dtype=np.float64)
         self.lib.oracle_fit(_f64(x), _f64(y), B, n, D, int(order), _f64(out))
+        return out
+
+
+    def demosaic(self, raw, out=None):
+        """raw: uint16 [I, H, W] (RGGB Bayer) -> uint16 [I, 3, H, W] (R, G, B planes)."""
+        raw = np.ascontiguousarray(raw, dtype=np.uint16)
+        I, H, W = raw.shape
+        if out is None:
+            out = np.empty((I, 3, H, W), dtype=np.uint16)
+        self.lib.oracle_demosaic(_u16(raw), I, H, W, _u16(out))
         return out
 
 

@@ -171,4 +171,62 @@ void oracle_fit(const double* x, const double* y, int32_t bands, int32_t points,
     }
 }
 
+// Case study 1 of the paper (§III.A): bilinear demosaicing of a Bayer image.
+// The paper describes the four cases (red pixel, blue pixel, green pixel in
+// a red row, green pixel in a blue row) and the averaging over the 8 direct
+// neighbours; it does not say how averages are rounded or what happens at
+// the border. Read here: integer averages rounded half up, and mirrored
+// indices outside the image.
+static int32_t mirror(int32_t i, int32_t n) {
+    if (i < 0) return -i;
+    if (i >= n) return 2 * (n - 1) - i;
+    return i;
+}
+
+void oracle_demosaic(const uint16_t* raw, int32_t images, int32_t height, int32_t width,
+                     uint16_t* rgb) {
+    const size_t plane = (size_t)height * (size_t)width;
+    for (int32_t k = 0; k < images; ++k) {
+        const uint16_t* im = raw + (size_t)k * plane;
+        uint16_t* out = rgb + (size_t)k * 3 * plane;
+        auto at = [&](int32_t r, int32_t c) -> uint32_t {
+            return im[(size_t)mirror(r, height) * (size_t)width + (size_t)mirror(c, width)];
+        };
+        for (int32_t r = 0; r < height; ++r) {
+            for (int32_t c = 0; c < width; ++c) {
+                const uint32_t self = at(r, c);
+                const uint32_t cross = at(r - 1, c) + at(r + 1, c) + at(r, c - 1) + at(r, c + 1);
+                const uint32_t diag = at(r - 1, c - 1) + at(r - 1, c + 1) + at(r + 1, c - 1)
+                                      + at(r + 1, c + 1);
+                const uint32_t horiz = at(r, c - 1) + at(r, c + 1);
+                const uint32_t vert = at(r - 1, c) + at(r + 1, c);
+                uint32_t R, G, B;
+                const bool red_row = (r % 2) == 0;
+                const bool red_col = (c % 2) == 0;
+                if (red_row && red_col) {          // red pixel
+                    R = self;
+                    G = (cross + 2) >> 2;
+                    B = (diag + 2) >> 2;
+                } else if (!red_row && !red_col) {  // blue pixel
+                    B = self;
+                    G = (cross + 2) >> 2;
+                    R = (diag + 2) >> 2;
+                } else if (red_row) {               // green pixel in a red row
+                    G = self;
+                    R = (horiz + 1) >> 1;
+                    B = (vert + 1) >> 1;
+                } else {                            // green pixel in a blue row
+                    G = self;
+                    B = (horiz + 1) >> 1;
+                    R = (vert + 1) >> 1;
+                }
+                const size_t p = (size_t)r * (size_t)width + (size_t)c;
+                out[p] = (uint16_t)R;
+                out[plane + p] = (uint16_t)G;
+                out[2 * plane + p] = (uint16_t)B;
+            }
+        }
+    }
+}
+
 }  // extern "C"

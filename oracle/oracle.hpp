@@ -28,8 +28,22 @@
 //   no FMA. coeffs[b][d][0..3] = a_0..a_m, then +0.0 above the order; a singular
 //   system (no nonzero pivot) gives NaN in all four.
 //
-// Parity pins (independent of this file) live in tests/test_oracle_pins.py and
-// tests/test_oracle_fit_pins.py.
+//   Bilinear Bayer demosaicing (§III.A, case study 1): a raw image [H][W] of
+//   16-bit samples behind an RGGB colour filter (R at even row and even
+//   column, B at odd row and odd column, G elsewhere) becomes three planes
+//   rgb[c][H][W]. Each pixel keeps its own sample for its own colour; each
+//   missing colour is the average of the neighbours of that colour among its
+//   8 direct neighbours, rounded half up in integers:
+//     at R: G = (N + S + E + W + 2) >> 2,  B = (NW + NE + SW + SE + 2) >> 2
+//     at B: G = (N + S + E + W + 2) >> 2,  R = (NW + NE + SW + SE + 2) >> 2
+//     at G in a red row:  R = (E + W + 1) >> 1,  B = (N + S + 1) >> 1
+//     at G in a blue row: B = (E + W + 1) >> 1,  R = (N + S + 1) >> 1
+//   Outside the image, rows and columns are mirrored about the edge sample
+//   (index -1 reads 1, index H reads H-2), which keeps the colour pattern.
+//   H and W are even.
+//
+// Parity pins (independent of this file) live in tests/test_oracle_pins.py,
+// tests/test_oracle_fit_pins.py and tests/test_oracle_demosaic_pins.py.
 #pragma once
 #include <stdint.h>
 
@@ -61,6 +75,11 @@ void oracle_pixel(const double* coeffs, const uint16_t* dn, int64_t lines,
 // y is [bands][points], coeffs is [bands][detectors][4]; 0 <= order <= 3.
 void oracle_fit(const double* x, const double* y, int32_t bands, int32_t points,
                 int32_t detectors, int32_t order, double* coeffs);
+
+// Bilinear demosaicing (definition above) of `images` raw images
+// [images][height][width] into rgb [images][3][height][width].
+void oracle_demosaic(const uint16_t* raw, int32_t images, int32_t height, int32_t width,
+                     uint16_t* rgb);
 
 #ifdef __cplusplus
 }

@@ -68,3 +68,11 @@ def test_calib_is_deterministic_and_shaped():
     # A detector's data do not depend on how many detectors are drawn.
     x3, _ = gen.calib(gen.BASE_SEED, 5, 0, 2, 6, 40, 1024)
     assert np.array_equal(x3, x1[:, :, :40])
+
+
+def test_bayer_is_deterministic():
+    a = gen.bayer(gen.BASE_SEED, 7, 0, 2, 64, 96)
+    b = gen.bayer(gen.BASE_SEED, 7, 0, 2, 64, 96, threads=1)
+    assert a.shape == (2, 64, 96) and a.dtype == np.uint16
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a[0], a[1])  # phases drawn per image

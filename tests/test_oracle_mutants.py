@@ -11,6 +11,7 @@ import oracle
 from oracle import build as obuild
 import pins
 import pins_fit
+import pins_demosaic
 
 SRC = os.path.join(os.path.dirname(obuild.__file__), "oracle.cpp")
 
@@ -57,6 +58,25 @@ MUTANTS_FIT = {
                            "                                    + (size_t)d];",
                            "const double xi = x[((size_t)b * (size_t)detectors + (size_t)d) * (size_t)points\n"
                            "                                    + (size_t)i];")],
+}
+
+
+# Plausible mistakes in the bilinear demosaicing (§III.A).
+MUTANTS_DEMOSAIC = {
+    "dm_truncating_average": [("R = self;\n                    G = (cross + 2) >> 2;",
+                               "R = self;\n                    G = cross >> 2;")],
+    "dm_green_red_row_swapped": [("G = self;\n                    R = (horiz + 1) >> 1;\n"
+                                  "                    B = (vert + 1) >> 1;",
+                                  "G = self;\n                    R = (vert + 1) >> 1;\n"
+                                  "                    B = (horiz + 1) >> 1;")],
+    "dm_edge_repeated": [("if (i < 0) return -i;", "if (i < 0) return -i - 1;"),
+                         ("if (i >= n) return 2 * (n - 1) - i;", "if (i >= n) return 2 * n - 1 - i;")],
+    "dm_pattern_bggr": [("const bool red_row = (r % 2) == 0;", "const bool red_row = (r % 2) == 1;"),
+                        ("const bool red_col = (c % 2) == 0;", "const bool red_col = (c % 2) == 1;")],
+    "dm_planes_swapped": [("out[p] = (uint16_t)R;", "out[p] = (uint16_t)B;"),
+                          ("out[2 * plane + p] = (uint16_t)B;", "out[2 * plane + p] = (uint16_t)R;")],
+    "dm_diag_for_green": [("B = self;\n                    G = (cross + 2) >> 2;",
+                           "B = self;\n                    G = (diag + 2) >> 2;")],
 }
 
 
@@ -107,3 +127,23 @@ def test_fit_mutant_is_caught(name, tmp_path):
             caught.append(pin.__name__)
             break
     assert caught, f"mutant {name} passed every fit pin"
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS_DEMOSAIC))
+def test_demosaic_mutant_is_caught(name, tmp_path):
+    src = open(SRC).read()
+    for old, new in MUTANTS_DEMOSAIC[name]:
+        assert src.count(old) == 1, f"mutation site not unique for {name}: {old!r}"
+        src = src.replace(old, new)
+    path = tmp_path / "oracle_mutant.cpp"
+    path.write_text(src)
+    lib = obuild.build(src=str(path), out=str(tmp_path / "liboracle_mutant.so"))
+    o = oracle.Oracle(lib)
+    caught = []
+    for pin in pins_demosaic.ALL_DEMOSAIC_PINS:
+        try:
+            pin(o)
+        except AssertionError:
+            caught.append(pin.__name__)
+            break
+    assert caught, f"mutant {name} passed every demosaicing pin"
