@@ -161,6 +161,36 @@ rc_status rc_correct_plan(const uint16_t* dn, const uint16_t* lut, int64_t lines
 rc_status rc_fit(const double* x, const double* y, int32_t bands, int32_t points,
                  int32_t detectors, int32_t order, double* coeffs, hipStream_t stream);
 
+/* ---- bilinear Bayer demosaicing ------------------------------------------------------- */
+
+/*
+ * Case study 1 of the paper (§III.A, bilinear interpolation based
+ * demosaicing). raw holds `images` mosaics of height x width 16-bit samples
+ * behind an RGGB colour filter (R at even row and even column, B at odd row
+ * and odd column, G elsewhere). Each output pixel keeps its own sample for
+ * its own colour; each missing colour is the average of that colour's
+ * samples among the pixel's 8 direct neighbours, rounded half up in
+ * integers: at R and B pixels, G from the 4 cross neighbours and the other
+ * of R/B from the 4 diagonal ones; at G pixels, the colour of its row from
+ * the 2 horizontal neighbours and the other from the 2 vertical ones. Rows
+ * and columns outside the image are mirrored about the edge sample (index -1
+ * reads 1, index n reads n - 2), which keeps the colour pattern. Exact
+ * integer arithmetic: results are bit-identical to any implementation of this
+ * definition.
+ *
+ *   raw     device, [images][height][width] uint16
+ *   rgb     device, [images][3][height][width] uint16, written (R, G, B planes)
+ *   height  even, >= 2;  width a multiple of 4, >= 4
+ *
+ * The caller owns both buffers (8-byte aligned, not overlapping); nothing is
+ * allocated; one kernel is enqueued on `stream`. RC_EINVAL (nothing enqueued)
+ * for negative sizes, odd height, width not a multiple of 4, null or
+ * misaligned pointers when there is work, overlap, or sizes that overflow.
+ * Zero images or an empty image: RC_OK, no work.
+ */
+rc_status rc_demosaic(const uint16_t* raw, int32_t images, int32_t height, int32_t width,
+                      uint16_t* rgb, hipStream_t stream);
+
 /* ---- autotuner and plan cache --------------------------------------------------------- */
 
 /*

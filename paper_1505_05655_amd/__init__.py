@@ -5,9 +5,10 @@ PyTorch provides device memory (tensors) and streams. There is no CPU
 fallback: importing this package fails if the library has not been built.
 
 Functions named like the C ABI (``rc_fit``, ``rc_lut_build``, ``rc_correct``,
-``rc_correct_plan``, ``rc_plan_for``) take device tensors or raw device
-pointers (ints) plus the same sizes as the C functions. ``fit``,
-``lut_build`` and ``correct`` are shape-checked conveniences on top of them.
+``rc_correct_plan``, ``rc_plan_for``, ``rc_demosaic``) take device tensors or
+raw device pointers (ints) plus the same sizes as the C functions. ``fit``,
+``lut_build``, ``correct`` and ``demosaic`` are shape-checked conveniences on
+top of them.
 
 uint16 data is carried in torch.int16 (or torch.uint16) tensors: only the
 bits matter and no arithmetic is done on them in Python.
@@ -123,6 +124,8 @@ _lib.rc_lut_build.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_lut_build.restype = ctypes.c_int
 _lib.rc_fit.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_fit.restype = ctypes.c_int
+_lib.rc_demosaic.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp]
+_lib.rc_demosaic.restype = ctypes.c_int
 _lib.rc_correct.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_correct.restype = ctypes.c_int
 _lib.rc_correct_plan.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, ctypes.POINTER(Plan), _vp]
@@ -209,6 +212,11 @@ def rc_lut_build(coeffs, bands, detectors, levels, lut, stream=None):
 def rc_fit(x, y, bands, points, detectors, order, coeffs, stream=None):
     _check(_lib.rc_fit(_ptr(x), _ptr(y), bands, points, detectors, order, _ptr(coeffs),
                        _stream(stream)), "rc_fit")
+
+
+def rc_demosaic(raw, images, height, width, rgb, stream=None):
+    _check(_lib.rc_demosaic(_ptr(raw), images, height, width, _ptr(rgb), _stream(stream)),
+           "rc_demosaic")
 
 
 def rc_correct(dn, lut, lines, detectors, bands, levels, out, stream=None):
@@ -424,6 +432,19 @@ def fit(x, y, order, out=None, stream=None):
     if out is None:
         out = torch.empty((B, D, 4), dtype=torch.float64, device=x.device)
     rc_fit(x.contiguous(), y.contiguous(), B, n, D, order, out, stream)
+    return out
+
+
+def demosaic(raw, out=None, stream=None):
+    """raw: 16-bit device tensor [I, H, W] (RGGB) -> [I, 3, H, W] R, G, B planes."""
+    if not _u16(raw) or raw.dim() != 3:
+        raise ValueError("raw must be a 16-bit tensor [images, height, width]")
+    I, H, W = raw.shape
+    if out is None:
+        out = torch.empty((I, 3, H, W), dtype=raw.dtype, device=raw.device)
+    if not _u16(out) or tuple(out.shape) != (I, 3, H, W):
+        raise ValueError("out must be a 16-bit tensor [images, 3, height, width]")
+    rc_demosaic(raw, I, H, W, out, stream)
     return out
 
 

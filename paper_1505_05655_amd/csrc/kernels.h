@@ -35,6 +35,10 @@ hipError_t launch_lut_build(const double* coeffs, int64_t rows, int32_t levels, 
 hipError_t launch_fit(const double* x, const double* y, int32_t bands, int32_t points,
                       int32_t detectors, int32_t order, double* coeffs, hipStream_t stream);
 
+// Bilinear Bayer demosaicing (arguments validated by rc_demosaic).
+hipError_t launch_demosaic(const uint16_t* raw, int32_t images, int32_t H, int32_t W,
+                           uint16_t* rgb, int cus, hipStream_t stream);
+
 // Correction with the given plan (already validated).
 hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,
                         hipStream_t stream);

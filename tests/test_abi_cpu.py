@@ -121,6 +121,28 @@ def test_fit_empty_is_noop():
     assert L.rc_fit(None, None, 3, 6, 0, 2, None, None) == rc.RC_OK
 
 
+@pytest.mark.parametrize("args", [
+    # raw, images, height, width, rgb
+    (None, 1, 4, 8, FAKE * 64),            # NULL raw
+    (FAKE, 1, 4, 8, None),                 # NULL rgb
+    (FAKE, -1, 4, 8, FAKE * 64),           # negative images
+    (FAKE, 1, -4, 8, FAKE * 64),           # negative height
+    (FAKE, 1, 3, 8, FAKE * 64),            # odd height
+    (FAKE, 1, 4, 6, FAKE * 64),            # width not a multiple of 4
+    (FAKE + 2, 1, 4, 8, FAKE * 64),        # raw not 8-byte aligned
+    (FAKE, 1, 4, 8, FAKE * 64 + 4),        # rgb not 8-byte aligned
+    (FAKE, 1, 4, 8, FAKE + 32),            # rgb overlaps raw
+    (FAKE, 1 << 20, 1 << 20, 1 << 20, FAKE * 64),  # sizes overflow
+])
+def test_demosaic_rejects(args):
+    assert L.rc_demosaic(*args, None) == rc.RC_EINVAL
+
+
+def test_demosaic_empty_is_noop():
+    assert L.rc_demosaic(None, 0, 4, 8, None, None) == rc.RC_OK
+    assert L.rc_demosaic(None, 2, 0, 8, None, None) == rc.RC_OK
+
+
 def test_correct_plan_requires_plan():
     assert L.rc_correct_plan(FAKE, FAKE * 64, 4, 4, 1, 1024, FAKE * 128, None, None) == rc.RC_EINVAL
 
