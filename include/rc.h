@@ -108,7 +108,8 @@ typedef struct {
     int32_t unroll;      /* lines in flight per lane: 4, 8 or 16 */
     int32_t chunk_lines; /* lines per tile, >= 1 */
     int32_t xcd_remap;   /* 1: place neighbouring tiles on the same XCD */
-    int32_t nontemporal; /* 1: streaming (non-temporal) image loads and stores */
+    int32_t nontemporal; /* image cache policy: 0 normal, 1 non-temporal loads and stores,
+                            2 non-temporal stores only */
 } rc_plan;
 
 /*

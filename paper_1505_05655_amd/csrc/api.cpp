@@ -149,7 +149,9 @@ void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t level
     p.threads = 512;
     p.unroll = 8;
     p.xcd_remap = 1;
-    p.nontemporal = p.strip >= 256 ? 1 : 0;
+    // Wide strips write long runs of each line: non-temporal stores pay there
+    // (measured); for narrower strips they cost more than they save.
+    p.nontemporal = p.strip >= 256 ? 2 : 0;
 
     const size_t lds_bytes = plan_lds_bytes(p.path, p.strip, levels);
     const int slots = plan_slots(p, lds_bytes, di);
@@ -188,6 +190,8 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
     if (plan.threads != 256 && plan.threads != 512 && plan.threads != 1024) return RC_EINVAL;
     if (plan.unroll != 4 && plan.unroll != 8 && plan.unroll != 16) return RC_EINVAL;
     if (plan.chunk_lines < 1) return RC_EINVAL;
+    if (plan.nontemporal < 0 || plan.nontemporal > 2) return RC_EINVAL;
+    if (plan.xcd_remap < 0 || plan.xcd_remap > 1) return RC_EINVAL;
     if (plan.strip / plan.vec > plan.threads) return RC_EINVAL;
     const size_t bytes = plan_lds_bytes(plan.path, plan.strip, levels);
     if (bytes > di.lds) return RC_EINVAL;

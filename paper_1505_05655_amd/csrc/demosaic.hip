@@ -7,10 +7,10 @@
 //
 // Layout and mapping: raw [images][H][W] uint16, rgb [images][3][H][W]. A
 // lane owns 4 consecutive columns (one 8-byte load per row, three 8-byte
-// stores per row, so a wave moves 512 contiguous bytes per instruction) and
-// walks down a band of rows with a three-row window in registers: each row
-// is loaded once, the next row's load is in flight while the current row is
-// computed. The left and right neighbour columns come from the adjacent lanes
+// non-temporal stores per row, so a wave moves 512 contiguous bytes per
+// instruction) and walks down a band of rows with a three-row window in
+// registers: each row is loaded once, the next row's load is in flight while
+// the current row is computed. The left and right neighbour columns come from the adjacent lanes
 // by lane shuffles; only the two lanes at a wave's edge load them. No LDS.
 #include <hip/hip_runtime.h>
 
@@ -134,9 +134,16 @@ __global__ __launch_bounds__(256) void k_demosaic(const uint16_t* __restrict__ r
         }
         if (valid) {
             const size_t o = (size_t)r * (size_t)W + (size_t)c0;
-            *(uint2*)(out + o) = make_uint2(R[0] | (R[1] << 16), R[2] | (R[3] << 16));
-            *(uint2*)(out + plane + o) = make_uint2(G[0] | (G[1] << 16), G[2] | (G[3] << 16));
-            *(uint2*)(out + 2 * plane + o) = make_uint2(B[0] | (B[1] << 16), B[2] | (B[3] << 16));
+            // Non-temporal: the planes are written once and not read back here.
+            uint32_t* q = (uint32_t*)(out + o);
+            __builtin_nontemporal_store(R[0] | (R[1] << 16), q);
+            __builtin_nontemporal_store(R[2] | (R[3] << 16), q + 1);
+            q = (uint32_t*)(out + plane + o);
+            __builtin_nontemporal_store(G[0] | (G[1] << 16), q);
+            __builtin_nontemporal_store(G[2] | (G[3] << 16), q + 1);
+            q = (uint32_t*)(out + 2 * plane + o);
+            __builtin_nontemporal_store(B[0] | (B[1] << 16), q);
+            __builtin_nontemporal_store(B[2] | (B[3] << 16), q + 1);
         }
         P = C;
         C = N;

@@ -92,39 +92,39 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
 typedef int i32x2 __attribute__((ext_vector_type(2)));
 
 // VEC pixels of one line through a buffer resource: per-lane byte offset
-// `vo` (VGPR) plus a wave-uniform line offset `so` (SGPR). NTH sets the
-// non-temporal cache policy.
-template <int VEC, bool NTH> struct Buf;
-template <bool NTH> struct Buf<1, NTH> {
+// `vo` (VGPR) plus a wave-uniform line offset `so` (SGPR). NT selects the
+// non-temporal cache policy: 0 none, 1 loads and stores, 2 stores only.
+template <int VEC, int NT> struct Buf;
+template <int NT> struct Buf<1, NT> {
     static __device__ __forceinline__ unsigned short ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
                                                         uint32_t so) {
         return (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so,
-                                                                    NTH ? 2 : 0);
+                                                                    NT == 1 ? 2 : 0);
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                               unsigned short v) {
-        __builtin_amdgcn_raw_buffer_store_b16((short)v, r, (int)vo, (int)so, NTH ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b16((short)v, r, (int)vo, (int)so, NT != 0 ? 2 : 0);
     }
 };
-template <bool NTH> struct Buf<2, NTH> {
+template <int NT> struct Buf<2, NT> {
     static __device__ __forceinline__ unsigned int ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
                                                       uint32_t so) {
         return (unsigned int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so,
-                                                                  NTH ? 2 : 0);
+                                                                  NT == 1 ? 2 : 0);
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                               unsigned int v) {
-        __builtin_amdgcn_raw_buffer_store_b32((int)v, r, (int)vo, (int)so, NTH ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b32((int)v, r, (int)vo, (int)so, NT != 0 ? 2 : 0);
     }
 };
-template <bool NTH> struct Buf<4, NTH> {
+template <int NT> struct Buf<4, NT> {
     static __device__ __forceinline__ u32x2 ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
                                                uint32_t so) {
-        return (u32x2)__builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, NTH ? 2 : 0);
+        return (u32x2)__builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, NT == 1 ? 2 : 0);
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                               u32x2 v) {
-        __builtin_amdgcn_raw_buffer_store_b64((i32x2)v, r, (int)vo, (int)so, NTH ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b64((i32x2)v, r, (int)vo, (int)so, NT != 0 ? 2 : 0);
     }
 };
 
@@ -136,7 +136,7 @@ template <bool NTH> struct Buf<4, NTH> {
 // which would force a wait on the prefetched loads). The prefetch past the
 // last pass falls outside the buffer range (loads of 0); offsets stay below
 // 2^31 because tiles are sized with two passes of slack.
-template <int VEC, int UNROLL, bool NTH, typename G>
+template <int VEC, int UNROLL, int NT, typename G>
 __device__ __forceinline__ void stream_lines(__amdgpu_buffer_rsrc_t rin,
                                              __amdgpu_buffer_rsrc_t rout, uint32_t vo,
                                              uint32_t line_stride, int passes, G gather) {
@@ -144,23 +144,23 @@ __device__ __forceinline__ void stream_lines(__amdgpu_buffer_rsrc_t rin,
     const uint32_t pass_bytes = UNROLL * line_stride;
     T a[UNROLL], b[UNROLL];
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) a[u] = Buf<VEC, NTH>::ld(rin, vo, u * line_stride);
+    for (int u = 0; u < UNROLL; ++u) a[u] = Buf<VEC, NT>::ld(rin, vo, u * line_stride);
     uint32_t so = 0;
     for (int k = 0; k < passes; k += 2) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-            b[u] = Buf<VEC, NTH>::ld(rin, vo, so + pass_bytes + u * line_stride);
+            b[u] = Buf<VEC, NT>::ld(rin, vo, so + pass_bytes + u * line_stride);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-            Buf<VEC, NTH>::st(rout, vo, so + u * line_stride, map_px<VEC>(a[u], gather));
+            Buf<VEC, NT>::st(rout, vo, so + u * line_stride, map_px<VEC>(a[u], gather));
         if (k + 1 >= passes) break;
         so += pass_bytes;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-            a[u] = Buf<VEC, NTH>::ld(rin, vo, so + pass_bytes + u * line_stride);
+            a[u] = Buf<VEC, NT>::ld(rin, vo, so + pass_bytes + u * line_stride);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-            Buf<VEC, NTH>::st(rout, vo, so + u * line_stride, map_px<VEC>(b[u], gather));
+            Buf<VEC, NT>::st(rout, vo, so + u * line_stride, map_px<VEC>(b[u], gather));
         so += pass_bytes;
     }
 }
@@ -217,7 +217,7 @@ enum TileMode { kRaw = 0, kGlobal = 1, kPacked = 2 };
 // W / VEC <= blockDim.x, and the LDS size of the mode. dn and out may be the
 // same buffer (in place): every pixel is read and then written by the same
 // lane, so they are deliberately not __restrict__.
-template <int VEC, int UNROLL, bool NTH, int MODE>
+template <int VEC, int UNROLL, int NT, int MODE>
 __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* __restrict__ lut,
                                            uint16_t* out, int64_t N, int D, int L, int logW,
                                            int b, int d0, int weff, int64_t n0, int64_t n1,
@@ -290,7 +290,7 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
         }
         __syncthreads();
         if (j < weff) {
-            stream_lines<VEC, UNROLL, NTH>(
+            stream_lines<VEC, UNROLL, NT>(
                 rin, rout, vo, line_stride, passes,
                 [&](int k, uint32_t d) { return g_raw(tile, d, top, logW, j + k); });
         }
@@ -298,7 +298,7 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
     } else if constexpr (MODE == kGlobal) {
         if (j < weff) {
             const uint16_t* lrow = strip_lut + (size_t)j * Lz;
-            stream_lines<VEC, UNROLL, NTH>(
+            stream_lines<VEC, UNROLL, NT>(
                 rin, rout, vo, line_stride, passes,
                 [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
         }
@@ -420,13 +420,13 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
         bad = __syncthreads_or(bad);
         if (j < weff) {
             if (!bad) {
-                stream_lines<VEC, UNROLL, NTH>(
+                stream_lines<VEC, UNROLL, NT>(
                     rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
                         return g_packed(planes, bases, d, top, logW, (k << logq) + lane);
                     });
             } else {
                 const uint16_t* lrow = strip_lut + (size_t)j * Lz;
-                stream_lines<VEC, UNROLL, NTH>(
+                stream_lines<VEC, UNROLL, NT>(
                     rin, rout, vo, line_stride, passes,
                     [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
             }
@@ -607,7 +607,7 @@ __device__ __forceinline__ void fused_tile(const double* __restrict__ coeffs, co
         if constexpr (MODE == kRaw) {
             const uint16_t* tile = (const uint16_t*)smem;
             if (j < weff) {
-                stream_lines<VEC, UNROLL, false>(
+                stream_lines<VEC, UNROLL, 0>(
                     rin, rout, vo, line_stride, passes,
                     [&](int k, uint32_t d) { return g_raw(tile, d, top, logW, j + k); });
             }
@@ -617,7 +617,7 @@ __device__ __forceinline__ void fused_tile(const double* __restrict__ coeffs, co
             const uint16_t* bases = (const uint16_t*)(planes + (size_t)NB * (1 << logW));
             if (!bad) {
                 if (j < weff) {
-                    stream_lines<VEC, UNROLL, false>(
+                    stream_lines<VEC, UNROLL, 0>(
                         rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
                             return g_packed(planes, bases, d, top, logW, (k << logq) + lane);
                         });
@@ -630,7 +630,7 @@ __device__ __forceinline__ void fused_tile(const double* __restrict__ coeffs, co
                 const __amdgpu_buffer_rsrc_t rl =
                     make_rsrc(lut + row0 * (size_t)L, (uint32_t)((size_t)weff * L * 2));
                 if (j < weff) {
-                    stream_lines<VEC, UNROLL, false>(
+                    stream_lines<VEC, UNROLL, 0>(
                         rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
                             return g_glb_l2(rl, (uint32_t)((j + k) * L * 2), d, top);
                         });

@@ -11,7 +11,7 @@
 
 namespace rc {
 
-template <int VEC, int UNROLL, bool NTH, int MODE>
+template <int VEC, int UNROLL, int NT, int MODE>
 __global__ __launch_bounds__(1024) void k_apply(ApplyParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x, p.xcds);
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(1024) void k_apply(ApplyParams p) {
     const int weff = min(W, p.detectors - d0);
     const int64_t n0 = (int64_t)c * p.chunk_lines;
     const int64_t n1 = min(p.lines, n0 + p.chunk_lines);
-    apply_tile<VEC, UNROLL, NTH, MODE>(p.dn, p.lut, p.out, p.lines, p.detectors, p.levels,
+    apply_tile<VEC, UNROLL, NT, MODE>(p.dn, p.lut, p.out, p.lines, p.detectors, p.levels,
                                        p.log_strip, b, d0, weff, n0, n1, smem, p.lut_vec != 0);
 }
 
@@ -40,20 +40,24 @@ typedef void (*ApplyKernel)(ApplyParams);
 
 namespace {
 
-// row[nontemporal * 3 + mode], mode = rc_path value (raw LDS, L2, packed LDS)
+// row[nontemporal * 3 + mode], mode = rc_path value (raw LDS, L2, packed LDS),
+// nontemporal = 0 (none), 1 (loads and stores), 2 (stores only)
 template <int VEC, int UNROLL>
 void fill_row(ApplyKernel* row) {
-    row[0] = k_apply<VEC, UNROLL, false, kRaw>;
-    row[1] = k_apply<VEC, UNROLL, false, kGlobal>;
-    row[2] = k_apply<VEC, UNROLL, false, kPacked>;
-    row[3] = k_apply<VEC, UNROLL, true, kRaw>;
-    row[4] = k_apply<VEC, UNROLL, true, kGlobal>;
-    row[5] = k_apply<VEC, UNROLL, true, kPacked>;
+    row[0] = k_apply<VEC, UNROLL, 0, kRaw>;
+    row[1] = k_apply<VEC, UNROLL, 0, kGlobal>;
+    row[2] = k_apply<VEC, UNROLL, 0, kPacked>;
+    row[3] = k_apply<VEC, UNROLL, 1, kRaw>;
+    row[4] = k_apply<VEC, UNROLL, 1, kGlobal>;
+    row[5] = k_apply<VEC, UNROLL, 1, kPacked>;
+    row[6] = k_apply<VEC, UNROLL, 2, kRaw>;
+    row[7] = k_apply<VEC, UNROLL, 2, kGlobal>;
+    row[8] = k_apply<VEC, UNROLL, 2, kPacked>;
 }
 
 // table[vec index][unroll index][nontemporal * 3 + mode]
 struct Table {
-    ApplyKernel k[3][3][6];
+    ApplyKernel k[3][3][9];
     Table() {
         fill_row<1, 4>(k[0][0]);
         fill_row<1, 8>(k[0][1]);
@@ -84,7 +88,7 @@ hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
     size_t worst_static = 0;
     for (int v = 0; v < 3; ++v)
         for (int u = 0; u < 3; ++u)
-            for (int m = 0; m < 6; ++m) {
+            for (int m = 0; m < 9; ++m) {
                 if (m % 3 == kGlobal) continue;
                 hipFuncAttributes attr;
                 hipError_t e = hipFuncGetAttributes(&attr, (const void*)t.k[v][u][m]);
@@ -95,7 +99,7 @@ hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
     const size_t dyn = bytes > worst_static ? bytes - worst_static : 0;
     for (int v = 0; v < 3; ++v)
         for (int u = 0; u < 3; ++u)
-            for (int m = 0; m < 6; ++m) {
+            for (int m = 0; m < 9; ++m) {
                 if (m % 3 == kGlobal) continue;
                 hipError_t e = hipFuncSetAttribute((const void*)t.k[v][u][m],
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -109,7 +113,7 @@ hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
 hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,
                         hipStream_t stream) {
     ApplyKernel k = table().k[vec_index(plan.vec)][unroll_index(plan.unroll)]
-                             [(plan.nontemporal ? 3 : 0) + plan.path];
+                             [plan.nontemporal * 3 + plan.path];
     hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3((unsigned)plan.threads),
                        plan.path == RC_PATH_L2 ? 0 : lds_bytes, stream, p);
     return hipGetLastError();

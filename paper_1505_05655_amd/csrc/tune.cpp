@@ -241,7 +241,7 @@ std::vector<rc_plan> candidates(int64_t lines, int32_t detectors, int32_t bands,
             for (int vec : vecs)
                 for (int threads : threads_l)
                     for (int unroll : unrolls)
-                        for (int nt = 0; nt < 2; ++nt)
+                        for (int nt = 0; nt < 3; ++nt)
                             for (int k : ks) add(path, W, vec, threads, unroll, nt, k);
     }
     // The L2 path: a few shapes, line chunks sized so an XCD's CUs share a strip.

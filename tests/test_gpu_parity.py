@@ -116,7 +116,7 @@ def plans_for(N, D, L):
     plans = []
     for path, strip, vec, threads, unroll, xcd, nt in itertools.product(
             (rc.RC_PATH_LDS, rc.RC_PATH_L2, rc.RC_PATH_PACKED), (8, 16, 64, 256), (1, 2, 4),
-            (256, 1024), (4, 16), (0, 1), (0, 1)):
+            (256, 1024), (4, 16), (0, 1), (0, 1, 2)):
         if path == rc.RC_PATH_LDS and strip * L * 2 > 128 * 1024:
             continue
         if path == rc.RC_PATH_PACKED and (L + 31) // 32 * strip * 10 > 128 * 1024:
@@ -221,6 +221,18 @@ def test_plan_rejected_when_lds_too_small():
                   xcd_remap=0, nontemporal=0)  # 64 x 4096 x 2 B = 512 KiB of LDS
     with pytest.raises(rc.RcError) as e:
         rc.correct(dn, lut, plan=bad)
+    assert e.value.status == rc.RC_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("nontemporal", 3), ("nontemporal", -1), ("xcd_remap", 2)])
+def test_plan_rejects_bad_policy(field, value):
+    dn = torch.zeros((1, 4, 64), dtype=torch.int16, device=dev())
+    lut = torch.zeros((1, 64, 1024), dtype=torch.int16, device=dev())
+    d = dict(path=rc.RC_PATH_PACKED, strip=64, vec=2, threads=256, unroll=4, chunk_lines=4,
+             xcd_remap=1, nontemporal=0)
+    d[field] = value
+    with pytest.raises(rc.RcError) as e:
+        rc.correct(dn, lut, plan=rc.Plan(**d))
     assert e.value.status == rc.RC_EINVAL
 
 
