@@ -439,7 +439,8 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
 // ---- fused LUT build + correction (batched requests) ------------------------------------
 
 // Writes entries [v0, v0 + n) of one LUT row (n <= 8, values in e) to global
-// memory: one 16-byte store when the 8 entries are aligned, else 16-bit stores.
+// memory: one 16-byte non-temporal store when the 8 entries are aligned (the
+// tile reads its LUT from LDS, not back from memory), else 16-bit stores.
 __device__ __forceinline__ void store_lut8(uint16_t* dst, const uint32_t* e, int n, bool vec16) {
     if (vec16 && n == 8) {
         u32x4 q;
@@ -447,7 +448,7 @@ __device__ __forceinline__ void store_lut8(uint16_t* dst, const uint32_t* e, int
         q.y = e[2] | (e[3] << 16);
         q.z = e[4] | (e[5] << 16);
         q.w = e[6] | (e[7] << 16);
-        *(u32x4*)dst = q;
+        __builtin_nontemporal_store(q, (u32x4*)dst);
     } else {
         for (int k = 0; k < n; ++k) dst[k] = (uint16_t)e[k];
     }

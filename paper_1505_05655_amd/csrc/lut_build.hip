@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_lut_build_rows(const double* __restrict
                 q.y = e[2] | (e[3] << 16);
                 q.z = e[4] | (e[5] << 16);
                 q.w = e[6] | (e[7] << 16);
-                *(u32x4*)dst = q;
+                *(u32x4*)dst = q;  // cacheable: the correction reads the LUT next
             } else {
                 for (int k = 0; k < n; ++k) dst[k] = (uint16_t)lut_entry(a0, a1, a2, a3, v0 + k, lim);
             }
