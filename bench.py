@@ -27,7 +27,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -486,6 +486,25 @@ def main():
     achieved = apply_bytes / (apply_avg * 1e-3) / 1e9
     value = px / (ms_per_step * 1e-3) / 1e9
 
+    # Cold caches, reported beside the headline (not part of it): before each
+    # of 10 extra steps a 512 MiB scratch write evicts the LUT from L2 and the
+    # 256 MB MALL; events around each kernel as above.
+    scratch = torch.empty(256 << 20, dtype=torch.int16, device=dev)
+    cold_b, cold_a = [], []
+    for _ in range(10):
+        with torch.cuda.stream(stream):
+            scratch.fill_(1)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
+        e[1].record(stream)
+        rc.rc_correct(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, stream)
+        e[2].record(stream)
+        stream.synchronize()
+        cold_b.append(e[0].elapsed_time(e[1]))
+        cold_a.append(e[1].elapsed_time(e[2]))
+    del scratch
+
     bit_exact = None
     cpu = None
     if not args.no_cpu_baseline or not args.no_verify:
@@ -554,11 +573,20 @@ def main():
         "bit_exact": bit_exact,
         "kernels": {
             "lut_apply_ms": {"mean": round(apply_avg, 4), "min": round(min(apply_ms), 4),
-                             "median": round(statistics.median(apply_ms), 4)},
+                             "median": round(statistics.median(apply_ms), 4),
+                             "p10": round(percentile(apply_ms, 10), 4),
+                             "p90": round(percentile(apply_ms, 90), 4)},
             "lut_apply_gpix_s": round(px / (apply_avg * 1e-3) / 1e9, 2),
             "lut_build_ms": {"mean": round(statistics.mean(build_ms), 4),
-                             "min": round(min(build_ms), 4)},
+                             "min": round(min(build_ms), 4),
+                             "median": round(statistics.median(build_ms), 4),
+                             "p10": round(percentile(build_ms, 10), 4),
+                             "p90": round(percentile(build_ms, 90), 4)},
             "lut_build_gb_s": round(build_bytes / (statistics.mean(build_ms) * 1e-3) / 1e9, 1),
+            "cold_caches": {"lut_apply_ms_median": round(statistics.median(cold_a), 4),
+                            "lut_build_ms_median": round(statistics.median(cold_b), 4),
+                            "steps": len(cold_a),
+                            "note": "512 MiB scratch write before each step"},
         },
         "fit": fit_res,
         "demosaic": demosaic_res,
