@@ -426,8 +426,8 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the path shards by band/detector strip with no exchange, see the design notes.",
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the work shards "
+              "by band and detector strip with no exchange between GPUs, so it is not run here.",
               file=sys.stderr)
         sys.exit(2)
 
