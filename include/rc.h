@@ -370,6 +370,80 @@ void rc_server_destroy(rc_server* s);
 void* rc_host_alloc(size_t bytes);
 void rc_host_free(void* p);
 
+/* ---- wire front end: the paper's client-server protocol --------------------------------- */
+
+/*
+ * The TCP front end of the paper's client-server framework (§II, Fig. 3):
+ * a client sends a 260-byte header, then the input data; the server runs the
+ * task on the GPU and answers with a header of the same layout followed by
+ * the result. Header fields (byte offsets; text fields NUL-padded):
+ *
+ *   [0, 29)    task flag: "LUT_CORRECTION", "BILINEAR_DEMOSAIC", "LSQ_FIT", "GPU_INFO"
+ *   [29]       '+' when data follows the header, '\0' when none does
+ *   [30, 230)  comma-separated parameters, key=value
+ *   [230, 260) output file name (the client's; echoed back, never opened here)
+ *   [260, ...) data, little-endian, laid out as for the C calls:
+ *     LUT_CORRECTION     bands=B,lines=N,detectors=D,levels=L[,lut=1]
+ *                        in:  coeffs f64 [B][D][4], then dn u16 [B][N][D]
+ *                        out: corrected u16 [B][N][D] (then the LUT u16 [B][D][L] if lut=1)
+ *     BILINEAR_DEMOSAIC  images=I,height=H,width=W
+ *                        in:  raw u16 [I][H][W];  out: rgb u16 [I][3][H][W]
+ *     LSQ_FIT            bands=B,points=n,detectors=D,order=m
+ *                        in:  x f64 [B][n][D], then y f64 [B][n];  out: coeffs f64 [B][D][4]
+ *     GPU_INFO           no parameters, no data;  out: an XML listing of the device
+ * The answer's parameter field reads "status=<rc_status name>,bytes=<result bytes>".
+ * Correction jobs of all connections go through one rc_server (continuous
+ * batching); the other tasks run on a stream of the connection.
+ */
+#define RC_WIRE_HEADER_BYTES 260
+
+typedef enum {
+    RC_TASK_LUT_CORRECTION = 1,
+    RC_TASK_BILINEAR_DEMOSAIC = 2,
+    RC_TASK_LSQ_FIT = 3,
+    RC_TASK_GPU_INFO = 4
+} rc_task;
+
+typedef struct {
+    int32_t task;          /* rc_task */
+    int32_t has_data;      /* the '+' flag */
+    char task_flag[30];    /* NUL-terminated copies of the text fields */
+    char params[201];
+    char out_name[31];
+    int64_t bands, lines, detectors, levels, points, order, images, height, width;
+    int32_t want_lut;
+    int32_t reserved;
+    uint64_t data_bytes;   /* input bytes that follow the header */
+    uint64_t result_bytes; /* bytes of the answer's data */
+} rc_wire_request;
+
+/* Parses and validates one request header (host only, no GPU). RC_EINVAL for
+ * an unknown task, a missing or malformed parameter, sizes out of range or
+ * overflowing, or a '+' flag that does not match the task. */
+rc_status rc_wire_parse(const uint8_t* header, rc_wire_request* req);
+
+typedef struct rc_wire rc_wire;
+
+typedef struct {
+    int32_t port;            /* TCP port; 0 picks a free one (see rc_wire_port) */
+    int32_t any_address;     /* 0: listen on 127.0.0.1 only; 1: on every interface */
+    uint64_t max_data_bytes; /* largest accepted request data; 0 = 8 GiB */
+    uint64_t arena_bytes;    /* device arena of the internal rc_server; 0 = its default */
+} rc_wire_opts;
+
+/* Starts listening on the current device (one accept thread, one thread per
+ * connection; a connection may send several requests in turn). o may be NULL
+ * for defaults. Errors: RC_EINVAL, RC_ENOMEM, RC_EHIP (device), RC_EBUSY
+ * (the port cannot be bound). */
+rc_status rc_wire_start(const rc_wire_opts* o, rc_wire** out);
+
+/* The port the server listens on (useful with port 0). */
+int32_t rc_wire_port(const rc_wire* w);
+
+/* Stops accepting, closes every connection after its current request, joins
+ * all threads and frees the server. NULL is ignored. */
+void rc_wire_stop(rc_wire* w);
+
 #ifdef __cplusplus
 }
 #endif

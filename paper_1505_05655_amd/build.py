@@ -22,7 +22,7 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC]
 SOURCES = ["lut_build.hip", "lut_apply.hip", "batch.hip", "fit.hip", "demosaic.hip", "api.cpp",
-           "tune.cpp", "serve.cpp"]
+           "tune.cpp", "serve.cpp", "wire.cpp"]
 
 
 def _compile(src):

@@ -1,0 +1,121 @@
+"""The wire front end's header (Fig. 3 of the paper) on the CPU: the client's
+encoder puts each field at its byte offset, and the library's parser
+(rc_wire_parse, host only) accepts well-formed requests with the right data
+sizes and rejects malformed ones."""
+import ctypes
+
+import pytest
+
+import paper_1505_05655_amd as rc
+from paper_1505_05655_amd import wire
+
+
+class WireRequest(ctypes.Structure):
+    """Mirrors rc_wire_request."""
+    _fields_ = [("task", ctypes.c_int32), ("has_data", ctypes.c_int32),
+                ("task_flag", ctypes.c_char * 30), ("params", ctypes.c_char * 201),
+                ("out_name", ctypes.c_char * 31),
+                ("bands", ctypes.c_int64), ("lines", ctypes.c_int64), ("detectors", ctypes.c_int64),
+                ("levels", ctypes.c_int64), ("points", ctypes.c_int64), ("order", ctypes.c_int64),
+                ("images", ctypes.c_int64), ("height", ctypes.c_int64), ("width", ctypes.c_int64),
+                ("want_lut", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("data_bytes", ctypes.c_uint64), ("result_bytes", ctypes.c_uint64)]
+
+
+L = rc.lib()
+L.rc_wire_parse.argtypes = [ctypes.c_char_p, ctypes.POINTER(WireRequest)]
+L.rc_wire_parse.restype = ctypes.c_int
+
+
+def parse(header):
+    r = WireRequest()
+    st = L.rc_wire_parse(header, ctypes.byref(r))
+    return st, r
+
+
+def test_field_offsets():
+    h = wire.encode_header("LSQ_FIT", {"bands": 1, "points": 6}, "out.bin", has_data=True)
+    assert len(h) == wire.HEADER_BYTES == 260
+    assert h[:7] == b"LSQ_FIT" and h[7:29] == b"\0" * 22
+    assert h[29:30] == b"+"
+    assert h[30:48] == b"bands=1,points=6\0\0"
+    assert h[230:237] == b"out.bin" and h[237:260] == b"\0" * 23
+    d = wire.decode_header(h)
+    assert d == {"task": "LSQ_FIT", "has_data": True, "params": {"bands": 1, "points": 6},
+                 "out_name": "out.bin"}
+    assert wire.encode_header("GPU_INFO")[29:30] == b"\0"
+
+
+def test_encoder_rejects_long_fields():
+    with pytest.raises(ValueError):
+        wire.encode_header("X" * 30)
+    with pytest.raises(ValueError):
+        wire.encode_header("GPU_INFO", "a=1" * 100)
+    with pytest.raises(ValueError):
+        wire.encode_header("GPU_INFO", out_name="n" * 31)
+
+
+@pytest.mark.parametrize("task,params,data,result,fields", [
+    ("LUT_CORRECTION", {"bands": 2, "lines": 10, "detectors": 7, "levels": 1024},
+     2 * 7 * 32 + 2 * 10 * 7 * 2, 2 * 10 * 7 * 2, {"bands": 2, "lines": 10, "levels": 1024}),
+    ("LUT_CORRECTION", {"bands": 1, "lines": 3, "detectors": 5, "levels": 4096, "lut": 1},
+     5 * 32 + 3 * 5 * 2, 3 * 5 * 2 + 5 * 4096 * 2, {"want_lut": 1}),
+    ("LUT_CORRECTION", {"bands": 1, "lines": 0, "detectors": 5, "levels": 2, "lut": 1},
+     5 * 32, 5 * 2 * 2, {"lines": 0}),
+    ("BILINEAR_DEMOSAIC", {"images": 2, "height": 4, "width": 8}, 2 * 4 * 8 * 2,
+     2 * 3 * 4 * 8 * 2, {"images": 2, "height": 4, "width": 8}),
+    ("LSQ_FIT", {"bands": 3, "points": 6, "detectors": 100, "order": 2},
+     3 * 6 * 100 * 8 + 3 * 6 * 8, 3 * 100 * 32, {"points": 6, "order": 2}),
+])
+def test_parse_valid(task, params, data, result, fields):
+    st, r = parse(wire.encode_header(task, params, "result.bin", has_data=True))
+    assert st == rc.RC_OK
+    assert r.task == wire.TASKS.index(task) + 1 and r.has_data == 1
+    assert r.data_bytes == data and r.result_bytes == result
+    assert r.out_name == b"result.bin" and r.task_flag == task.encode()
+    for k, v in fields.items():
+        assert getattr(r, k) == v, k
+
+
+def test_parse_gpu_info():
+    st, r = parse(wire.encode_header("GPU_INFO", None, "gpus.xml"))
+    assert st == rc.RC_OK and r.task == 4 and r.data_bytes == 0 and r.has_data == 0
+
+
+def raw_header(task=b"LSQ_FIT", flag=b"+", params=b"bands=1,points=2,detectors=1,order=1",
+               out=b"o"):
+    h = bytearray(260)
+    h[0:len(task)] = task
+    h[29:30] = flag
+    h[30:30 + len(params)] = params
+    h[230:230 + len(out)] = out
+    return bytes(h)
+
+
+@pytest.mark.parametrize("header", [
+    raw_header(task=b"LUT_GENERATION"),                                  # unknown task
+    raw_header(task=b"lsq_fit"),                                         # task flags are exact
+    raw_header(flag=b"*"),                                               # flag neither '+' nor NUL
+    raw_header(flag=b"\0"),                                              # data expected, flag says none
+    raw_header(params=b"bands=1,points=2,detectors=1"),                  # missing order
+    raw_header(params=b"bands=1,points=2,detectors=1,order=1,x=2"),      # unknown key
+    raw_header(params=b"bands=1,bands=1,points=2,detectors=1,order=1"),  # duplicate key
+    raw_header(params=b"bands=1,points=two,detectors=1,order=1"),        # not a number
+    raw_header(params=b"bands=1,points=2,detectors=1,order=-1"),         # negative
+    raw_header(params=b"bands=1,points=2,detectors=1,order=1,"),         # trailing comma
+    raw_header(params=b"bands=1,points=2,detectors=1,order=2"),          # points < order + 1
+    raw_header(params=b"bands=1,points=2,detectors=1,order=4"),          # order > 3
+    raw_header(params=b"bands=0,points=2,detectors=1,order=1"),          # no bands
+    raw_header(task=b"BILINEAR_DEMOSAIC", params=b"images=1,height=3,width=8"),   # odd height
+    raw_header(task=b"BILINEAR_DEMOSAIC", params=b"images=1,height=4,width=6"),   # width % 4
+    raw_header(task=b"LUT_CORRECTION", params=b"bands=1,lines=1,detectors=1,levels=1"),
+    raw_header(task=b"LUT_CORRECTION", params=b"bands=1,lines=1,detectors=1,levels=1024,lut=2"),
+    raw_header(task=b"LUT_CORRECTION",
+               params=b"bands=2147483647,lines=137438953408,detectors=2147483647,levels=1024"),
+    raw_header(task=b"GPU_INFO", flag=b"+", params=b""),                 # GPU_INFO takes no data
+    raw_header(task=b"GPU_INFO", flag=b"\0", params=b"a=1"),             # nor parameters
+    raw_header(task=b"LSQ_FIT\0X"),                                      # junk after the NUL
+])
+def test_parse_rejects(header):
+    st, _ = parse(header)
+    assert st == rc.RC_EINVAL
