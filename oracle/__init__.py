@@ -37,6 +37,8 @@ def _load(path=None):
     lib.oracle_fit.restype = None
     lib.oracle_demosaic.argtypes = [u16p, i32, i32, i32, u16p]
     lib.oracle_demosaic.restype = None
+    lib.oracle_demosaic_gradient.argtypes = [u16p, i32, i32, i32, u16p]
+    lib.oracle_demosaic_gradient.restype = None
     if path is None:
         _lib = lib
     return lib
@@ -117,6 +119,16 @@ class Oracle:
         if out is None:
             out = np.empty((I, 3, H, W), dtype=np.uint16)
         self.lib.oracle_demosaic(_u16(raw), I, H, W, _u16(out))
+        return out
+
+
+    def demosaic_gradient(self, raw, out=None):
+        """raw: uint16 [I, H, W] (RGGB) -> uint16 [I, 3, H, W], adaptive colour plane."""
+        raw = np.ascontiguousarray(raw, dtype=np.uint16)
+        I, H, W = raw.shape
+        if out is None:
+            out = np.empty((I, 3, H, W), dtype=np.uint16)
+        self.lib.oracle_demosaic_gradient(_u16(raw), I, H, W, _u16(out))
         return out
 
 

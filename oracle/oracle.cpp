@@ -16,6 +16,7 @@
 #include "oracle.hpp"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstddef>
 
 extern "C" {
@@ -224,6 +225,99 @@ void oracle_demosaic(const uint16_t* raw, int32_t images, int32_t height, int32_
                 out[p] = (uint16_t)R;
                 out[plane + p] = (uint16_t)G;
                 out[2 * plane + p] = (uint16_t)B;
+            }
+        }
+    }
+}
+
+// Gradient-based demosaicing: the paper lists it beside bilinear demosaicing
+// (§II) without describing it; the method followed is Hamilton & Adams'
+// adaptive colour plane interpolation (U.S. Patent 5,629,734): interpolate
+// green along the direction of the smaller gradient, with a second-order
+// correction from the pixel's own colour, then red and blue from colour
+// differences with the interpolated green. Integer arithmetic as defined in
+// oracle.hpp.
+static int32_t clamp16(int32_t v) { return v < 0 ? 0 : (v > 65535 ? 65535 : v); }
+
+void oracle_demosaic_gradient(const uint16_t* raw, int32_t images, int32_t height,
+                              int32_t width, uint16_t* rgb) {
+    const size_t plane = (size_t)height * (size_t)width;
+    for (int32_t k = 0; k < images; ++k) {
+        const uint16_t* im = raw + (size_t)k * plane;
+        uint16_t* out = rgb + (size_t)k * 3 * plane;
+        uint16_t* gp = out + plane;  // the green plane, written by stage 1
+        auto at = [&](int32_t r, int32_t c) -> int32_t {
+            return im[(size_t)mirror(r, height) * (size_t)width + (size_t)mirror(c, width)];
+        };
+        auto g_at = [&](int32_t r, int32_t c) -> int32_t {
+            return gp[(size_t)mirror(r, height) * (size_t)width + (size_t)mirror(c, width)];
+        };
+        // Stage 1: green everywhere.
+        for (int32_t r = 0; r < height; ++r) {
+            for (int32_t c = 0; c < width; ++c) {
+                const bool green = ((r + c) % 2) == 1;
+                int32_t G;
+                if (green) {
+                    G = at(r, c);
+                } else {
+                    const int32_t C = at(r, c);
+                    const int32_t gl = at(r, c - 1), gr = at(r, c + 1);
+                    const int32_t gu = at(r - 1, c), gd = at(r + 1, c);
+                    const int32_t lh = 2 * C - at(r, c - 2) - at(r, c + 2);
+                    const int32_t lv = 2 * C - at(r - 2, c) - at(r + 2, c);
+                    const int32_t dh = std::abs(gl - gr) + std::abs(lh);
+                    const int32_t dv = std::abs(gu - gd) + std::abs(lv);
+                    if (dh < dv) G = (2 * (gl + gr) + lh + 2) >> 2;
+                    else if (dv < dh) G = (2 * (gu + gd) + lv + 2) >> 2;
+                    else G = (2 * (gl + gr + gu + gd) + lh + lv + 4) >> 3;
+                    G = clamp16(G);
+                }
+                gp[(size_t)r * (size_t)width + (size_t)c] = (uint16_t)G;
+            }
+        }
+        // Stage 2: red and blue from colour differences with the green plane.
+        for (int32_t r = 0; r < height; ++r) {
+            for (int32_t c = 0; c < width; ++c) {
+                const size_t p = (size_t)r * (size_t)width + (size_t)c;
+                const int32_t self = at(r, c);
+                const int32_t g0 = g_at(r, c);
+                const bool in_red_row = (r & 1) == 0;
+                const bool in_red_col = (c & 1) == 0;
+                int32_t red, blue;
+                // Colour X at a green pixel from neighbours (r1, c1) and (r2, c2).
+                auto pair = [&](int32_t r1, int32_t c1, int32_t r2, int32_t c2) {
+                    return clamp16((at(r1, c1) + at(r2, c2) + 2 * g0 - g_at(r1, c1)
+                                    - g_at(r2, c2) + 1) >> 1);
+                };
+                // Colour X at an R or B pixel from its four diagonal neighbours.
+                auto diagonal = [&]() {
+                    const int32_t n1 = at(r - 1, c - 1), n2 = at(r + 1, c + 1);
+                    const int32_t p1 = at(r - 1, c + 1), p2 = at(r + 1, c - 1);
+                    const int32_t ln = 2 * g0 - g_at(r - 1, c - 1) - g_at(r + 1, c + 1);
+                    const int32_t lp = 2 * g0 - g_at(r - 1, c + 1) - g_at(r + 1, c - 1);
+                    const int32_t dn = std::abs(n1 - n2) + std::abs(ln);
+                    const int32_t dp = std::abs(p1 - p2) + std::abs(lp);
+                    int32_t v;
+                    if (dn < dp) v = (n1 + n2 + ln + 1) >> 1;
+                    else if (dp < dn) v = (p1 + p2 + lp + 1) >> 1;
+                    else v = (n1 + n2 + p1 + p2 + ln + lp + 2) >> 2;
+                    return clamp16(v);
+                };
+                if (in_red_row && in_red_col) {          // red pixel
+                    red = self;
+                    blue = diagonal();
+                } else if (!in_red_row && !in_red_col) {  // blue pixel
+                    blue = self;
+                    red = diagonal();
+                } else if (in_red_row) {               // green pixel in a red row
+                    red = pair(r, c - 1, r, c + 1);
+                    blue = pair(r - 1, c, r + 1, c);
+                } else {                            // green pixel in a blue row
+                    blue = pair(r, c - 1, r, c + 1);
+                    red = pair(r - 1, c, r + 1, c);
+                }
+                out[p] = (uint16_t)red;
+                out[2 * plane + p] = (uint16_t)blue;
             }
         }
     }

@@ -42,6 +42,25 @@
 //   (index -1 reads 1, index H reads H-2), which keeps the colour pattern.
 //   H and W are even.
 //
+//   Gradient-based demosaicing (named in the paper's task list, §II; the method
+//   is Hamilton & Adams' adaptive colour plane interpolation, U.S. Patent
+//   5,629,734, 1997), same filter, borders and layout, integer arithmetic:
+//   stage 1, green at R and B pixels (C = own colour, Cl2/Cr2/Cu2/Cd2 the same
+//   colour two pixels away, Gl/Gr/Gu/Gd the green neighbours):
+//     dH = |Gl - Gr| + |2C - Cl2 - Cr2|,  dV = |Gu - Gd| + |2C - Cu2 - Cd2|
+//     dH < dV:  G = (2 (Gl + Gr) + 2C - Cl2 - Cr2 + 2) >> 2
+//     dV < dH:  G = (2 (Gu + Gd) + 2C - Cu2 - Cd2 + 2) >> 2
+//     equal:    G = (2 (Gl + Gr + Gu + Gd) + 4C - Cl2 - Cr2 - Cu2 - Cd2 + 4) >> 3
+//   stage 2, with the green plane G' of stage 1 (G' = G at green pixels):
+//     at a green pixel, each missing colour X from its two neighbours X1, X2
+//     (horizontal for the colour of the row, vertical for the other):
+//       X = (X1 + X2 + 2 G - G'1 - G'2 + 1) >> 1
+//     at a B (R) pixel, R (B) from the diagonal pair with the smaller
+//       |X1 - X2| + |2 G' - G'1 - G'2| (both pairs when equal:
+//       (sum of 4 X + 4 G' - sum of 4 G' + 2) >> 2), else (X1 + X2 + 2 G' - G'1 - G'2 + 1) >> 1
+//   >> is an arithmetic shift (floor); every interpolated value is clamped to
+//   [0, 65535]. H and W are even and at least 4.
+//
 // Parity pins (independent of this file) live in tests/test_oracle_pins.py,
 // tests/test_oracle_fit_pins.py and tests/test_oracle_demosaic_pins.py.
 #pragma once
@@ -80,6 +99,10 @@ void oracle_fit(const double* x, const double* y, int32_t bands, int32_t points,
 // [images][height][width] into rgb [images][3][height][width].
 void oracle_demosaic(const uint16_t* raw, int32_t images, int32_t height, int32_t width,
                      uint16_t* rgb);
+
+// Gradient-based (adaptive colour plane) demosaicing, definition above.
+void oracle_demosaic_gradient(const uint16_t* raw, int32_t images, int32_t height,
+                              int32_t width, uint16_t* rgb);
 
 #ifdef __cplusplus
 }

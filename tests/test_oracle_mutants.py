@@ -12,6 +12,7 @@ from oracle import build as obuild
 import pins
 import pins_fit
 import pins_demosaic
+import pins_demosaic_gradient
 
 SRC = os.path.join(os.path.dirname(obuild.__file__), "oracle.cpp")
 
@@ -77,6 +78,27 @@ MUTANTS_DEMOSAIC = {
                           ("out[2 * plane + p] = (uint16_t)B;", "out[2 * plane + p] = (uint16_t)R;")],
     "dm_diag_for_green": [("B = self;\n                    G = (cross + 2) >> 2;",
                            "B = self;\n                    G = (diag + 2) >> 2;")],
+}
+
+MUTANTS_GRADIENT = {
+    "gr_direction_swapped": [("if (dh < dv) G = (2 * (gl + gr) + lh + 2) >> 2;",
+                              "if (dh > dv) G = (2 * (gl + gr) + lh + 2) >> 2;")],
+    "gr_no_laplacian": [("if (dh < dv) G = (2 * (gl + gr) + lh + 2) >> 2;",
+                         "if (dh < dv) G = (2 * (gl + gr) + 2) >> 2;")],
+    "gr_laplacian_sign": [("const int32_t lv = 2 * C - at(r - 2, c) - at(r + 2, c);",
+                           "const int32_t lv = at(r - 2, c) + at(r + 2, c) - 2 * C;")],
+    "gr_tie_horizontal": [("else G = (2 * (gl + gr + gu + gd) + lh + lv + 4) >> 3;",
+                           "else G = (2 * (gl + gr) + lh + 2) >> 2;")],
+    "gr_gradient_no_abs": [("std::abs(gl - gr)", "(gl - gr)")],
+    "gr_no_clamp": [("G = clamp16(G);", "")],
+    "gr_pair_raw_green": [("2 * g0 - g_at(r1, c1)", "2 * g0 - at(r1, c1)")],
+    "gr_own_green_raw": [("const int32_t g0 = g_at(r, c);", "const int32_t g0 = at(r, c);")],
+    "gr_diagonals_swapped": [("if (dn < dp) v = (n1 + n2 + ln + 1) >> 1;",
+                              "if (dn > dp) v = (n1 + n2 + ln + 1) >> 1;")],
+    "gr_diag_tie_truncates": [("else v = (n1 + n2 + p1 + p2 + ln + lp + 2) >> 2;",
+                               "else v = (n1 + n2 + p1 + p2 + ln + lp) >> 2;")],
+    "gr_green_pairs_swapped": [("red = pair(r, c - 1, r, c + 1);\n                    blue = pair(r - 1, c, r + 1, c);",
+                                "red = pair(r - 1, c, r + 1, c);\n                    blue = pair(r, c - 1, r, c + 1);")],
 }
 
 
@@ -147,3 +169,23 @@ def test_demosaic_mutant_is_caught(name, tmp_path):
             caught.append(pin.__name__)
             break
     assert caught, f"mutant {name} passed every demosaicing pin"
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS_GRADIENT))
+def test_gradient_mutant_is_caught(name, tmp_path):
+    src = open(SRC).read()
+    for old, new in MUTANTS_GRADIENT[name]:
+        assert src.count(old) == 1, f"mutation site not unique for {name}: {old!r}"
+        src = src.replace(old, new)
+    path = tmp_path / "oracle_mutant.cpp"
+    path.write_text(src)
+    lib = obuild.build(src=str(path), out=str(tmp_path / "liboracle_mutant.so"))
+    o = oracle.Oracle(lib)
+    caught = []
+    for pin in pins_demosaic_gradient.ALL_GRADIENT_PINS:
+        try:
+            pin(o)
+        except AssertionError:
+            caught.append(pin.__name__)
+            break
+    assert caught, f"mutant {name} passed every gradient demosaicing pin"
