@@ -192,6 +192,45 @@ rc_status rc_fit(const double* x, const double* y, int32_t bands, int32_t points
 rc_status rc_demosaic(const uint16_t* raw, int32_t images, int32_t height, int32_t width,
                       uint16_t* rgb, hipStream_t stream);
 
+/* ---- gradient-based Bayer demosaicing ------------------------------------------------- */
+
+/*
+ * The gradient interpolation based demosaicing the paper lists beside the
+ * bilinear one (§II, §III.A), which it names without giving steps; the method
+ * is Hamilton and Adams' adaptive colour plane interpolation (U.S. Patent
+ * 5,629,734). Same mosaic, layout and mirrored borders as rc_demosaic (index
+ * -1 reads 1, -2 reads 2, n reads n - 2, n + 1 reads n - 3). Integer
+ * arithmetic, ">>" an arithmetic shift:
+ *
+ *   green at an R or B pixel with own sample C, green neighbours Gl Gr Gu Gd
+ *   and same-colour samples two away Cl Cr Cu Cd:
+ *     lh = 2C - Cl - Cr,  lv = 2C - Cu - Cd
+ *     dH = |Gl - Gr| + |lh|,  dV = |Gu - Gd| + |lv|
+ *     dH < dV: (2 (Gl + Gr) + lh + 2) >> 2;  dV < dH: (2 (Gu + Gd) + lv + 2) >> 2
+ *     equal:   (2 (Gl + Gr + Gu + Gd) + lh + lv + 4) >> 3
+ *   with G' that green plane (the sample itself at G pixels):
+ *     at a G pixel, the colour of its row from the horizontal pair X1, X2 and
+ *     the other colour from the vertical pair: (X1 + X2 + 2 G - G'1 - G'2 + 1) >> 1
+ *     at an R (B) pixel, B (R) from the diagonal pair with the smaller
+ *     |X1 - X2| + |2 G' - G'1 - G'2|, as (X1 + X2 + 2 G' - G'1 - G'2 + 1) >> 1,
+ *     or, when both are equal, (X1 + X2 + X3 + X4 + 4 G' - G'1 - G'2 - G'3 - G'4 + 2) >> 2
+ *   every interpolated value clamped to [0, 65535].
+ *
+ * Results are bit-identical to any implementation of this definition.
+ *
+ *   raw     device, [images][height][width] uint16
+ *   rgb     device, [images][3][height][width] uint16, written (R, G, B planes)
+ *   height  even, >= 4;  width a multiple of 4, >= 4
+ *
+ * The caller owns both buffers (8-byte aligned, not overlapping); nothing is
+ * allocated; one kernel is enqueued on `stream`. RC_EINVAL (nothing enqueued)
+ * for negative sizes, odd height or height 2, width not a multiple of 4, null
+ * or misaligned pointers when there is work, overlap, or sizes that overflow.
+ * Zero images or an empty image: RC_OK, no work.
+ */
+rc_status rc_demosaic_gradient(const uint16_t* raw, int32_t images, int32_t height,
+                               int32_t width, uint16_t* rgb, hipStream_t stream);
+
 /* ---- autotuner and plan cache --------------------------------------------------------- */
 
 /*

@@ -5,8 +5,8 @@ PyTorch provides device memory (tensors) and streams. There is no CPU
 fallback: importing this package fails if the library has not been built.
 
 Functions named like the C ABI (``rc_fit``, ``rc_lut_build``, ``rc_correct``,
-``rc_correct_plan``, ``rc_plan_for``, ``rc_demosaic``) take device tensors or
-raw device pointers (ints) plus the same sizes as the C functions. ``fit``,
+``rc_correct_plan``, ``rc_plan_for``, ``rc_demosaic``, ``rc_demosaic_gradient``) take
+device tensors or raw device pointers (ints) plus the same sizes as the C functions. ``fit``,
 ``lut_build``, ``correct`` and ``demosaic`` are shape-checked conveniences on
 top of them.
 
@@ -126,6 +126,8 @@ _lib.rc_fit.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_fit.restype = ctypes.c_int
 _lib.rc_demosaic.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_demosaic.restype = ctypes.c_int
+_lib.rc_demosaic_gradient.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp]
+_lib.rc_demosaic_gradient.restype = ctypes.c_int
 _lib.rc_correct.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_correct.restype = ctypes.c_int
 _lib.rc_correct_plan.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, ctypes.POINTER(Plan), _vp]
@@ -217,6 +219,11 @@ def rc_fit(x, y, bands, points, detectors, order, coeffs, stream=None):
 def rc_demosaic(raw, images, height, width, rgb, stream=None):
     _check(_lib.rc_demosaic(_ptr(raw), images, height, width, _ptr(rgb), _stream(stream)),
            "rc_demosaic")
+
+
+def rc_demosaic_gradient(raw, images, height, width, rgb, stream=None):
+    _check(_lib.rc_demosaic_gradient(_ptr(raw), images, height, width, _ptr(rgb),
+                                     _stream(stream)), "rc_demosaic_gradient")
 
 
 def rc_correct(dn, lut, lines, detectors, bands, levels, out, stream=None):
@@ -435,8 +442,11 @@ def fit(x, y, order, out=None, stream=None):
     return out
 
 
-def demosaic(raw, out=None, stream=None):
-    """raw: 16-bit device tensor [I, H, W] (RGGB) -> [I, 3, H, W] R, G, B planes."""
+def demosaic(raw, out=None, stream=None, method="bilinear"):
+    """raw: 16-bit device tensor [I, H, W] (RGGB) -> [I, 3, H, W] R, G, B planes.
+    method: "bilinear" (rc_demosaic) or "gradient" (rc_demosaic_gradient)."""
+    if method not in ("bilinear", "gradient"):
+        raise ValueError("method must be 'bilinear' or 'gradient'")
     if not _u16(raw) or raw.dim() != 3:
         raise ValueError("raw must be a 16-bit tensor [images, height, width]")
     I, H, W = raw.shape
@@ -444,7 +454,8 @@ def demosaic(raw, out=None, stream=None):
         out = torch.empty((I, 3, H, W), dtype=raw.dtype, device=raw.device)
     if not _u16(out) or tuple(out.shape) != (I, 3, H, W):
         raise ValueError("out must be a 16-bit tensor [images, 3, height, width]")
-    rc_demosaic(raw, I, H, W, out, stream)
+    call = rc_demosaic if method == "bilinear" else rc_demosaic_gradient
+    call(raw, I, H, W, out, stream)
     return out
 
 

@@ -21,8 +21,8 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=
          "-fno-fast-math", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC]
-SOURCES = ["lut_build.hip", "lut_apply.hip", "batch.hip", "fit.hip", "demosaic.hip", "api.cpp",
-           "tune.cpp", "serve.cpp", "wire.cpp"]
+SOURCES = ["lut_build.hip", "lut_apply.hip", "batch.hip", "fit.hip", "demosaic.hip",
+           "demosaic_gradient.hip", "api.cpp", "tune.cpp", "serve.cpp", "wire.cpp"]
 
 
 def _compile(src):

@@ -39,6 +39,11 @@ hipError_t launch_fit(const double* x, const double* y, int32_t bands, int32_t p
 hipError_t launch_demosaic(const uint16_t* raw, int32_t images, int32_t H, int32_t W,
                            uint16_t* rgb, int cus, hipStream_t stream);
 
+// Gradient-based (adaptive colour plane) demosaicing (arguments validated by
+// rc_demosaic_gradient).
+hipError_t launch_demosaic_gradient(const uint16_t* raw, int32_t images, int32_t H, int32_t W,
+                                    uint16_t* rgb, int cus, hipStream_t stream);
+
 // Correction with the given plan (already validated).
 hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,
                         hipStream_t stream);

@@ -196,3 +196,26 @@ def test_server_argument_checks():
     assert L.rc_server_wait(None, 1, None) == rc.RC_EINVAL
     assert L.rc_server_poll(None, 1, None) == rc.RC_EINVAL
     L.rc_server_destroy(None)
+
+
+@pytest.mark.parametrize("args", [
+    # raw, images, height, width, rgb
+    (None, 1, 4, 8, FAKE * 64),            # NULL raw
+    (FAKE, 1, 4, 8, None),                 # NULL rgb
+    (FAKE, -1, 4, 8, FAKE * 64),           # negative images
+    (FAKE, 1, -4, 8, FAKE * 64),           # negative height
+    (FAKE, 1, 5, 8, FAKE * 64),            # odd height
+    (FAKE, 1, 2, 8, FAKE * 64),            # height 2: the stencil reaches two rows
+    (FAKE, 1, 4, 6, FAKE * 64),            # width not a multiple of 4
+    (FAKE + 2, 1, 4, 8, FAKE * 64),        # raw not 8-byte aligned
+    (FAKE, 1, 4, 8, FAKE * 64 + 4),        # rgb not 8-byte aligned
+    (FAKE, 1, 4, 8, FAKE + 32),            # rgb overlaps raw
+    (FAKE, 1 << 20, 1 << 20, 1 << 20, FAKE * 64),  # sizes overflow
+])
+def test_demosaic_gradient_rejects(args):
+    assert L.rc_demosaic_gradient(*args, None) == rc.RC_EINVAL
+
+
+def test_demosaic_gradient_empty_is_noop():
+    assert L.rc_demosaic_gradient(None, 0, 4, 8, None, None) == rc.RC_OK
+    assert L.rc_demosaic_gradient(None, 2, 0, 8, None, None) == rc.RC_OK
