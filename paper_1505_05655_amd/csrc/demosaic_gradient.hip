@@ -20,9 +20,10 @@
 // Stage 1 reaches two rows and columns, stage 2 one more, so a lane keeps a
 // window of five raw rows (r-1 .. r+3) and three green rows (r-1 .. r+1) in
 // registers: per output row r it unpacks raw row r+3 (loaded during the
-// previous row), starts the load of row r+4, computes green row r+1 and
-// finishes row r. The window is a ring of five slots, and the row loop is
-// unrolled five times so the ring rotates by renaming, not by register moves.
+// two previous rows), starts the load of row r+5, computes green row r+1 and
+// finishes row r. The window is a ring of six slots, and the row loop is
+// unrolled six times so the ring rotates by renaming, not by register moves,
+// and the colour parity of every row is a compile-time constant.
 // Neighbour columns come from the adjacent lanes by lane shuffles; the two
 // lanes at a wave's edge load the 4 columns beyond it instead, and compute the
 // one green value beyond the wave that stage 2 needs (at column c0-1 in B
@@ -33,6 +34,7 @@
 
 #include <cstdint>
 
+#include "device_ops.h"
 #include "kernels.h"
 #include "rc.h"
 #include "runtime.h"
@@ -44,18 +46,50 @@ __device__ __forceinline__ int mirror_index(int i, int n) {
     return i < 0 ? -i : (i >= n ? 2 * (n - 1) - i : i);
 }
 
+// |a - b| + c on unsigned operands, one instruction.
+__device__ __forceinline__ uint32_t sad(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Lane i receives lane i-1's value (lane 0 keeps `old`), or lane i+1's (lane 63 keeps `old`).
+__device__ __forceinline__ uint32_t from_lower_lane(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t from_upper_lane(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x130, 0xf, 0xf, false);
+}
+
+// Per-lane constants of the column mapping. Rows are read and written through
+// buffer resources that span exactly one image row, so accesses of idle lanes
+// (c0 >= W) and of edge loads beyond the image read 0 and write nothing.
+struct Lane {
+    uint32_t off;       // byte offset of the lane's 4 samples in a row
+    uint32_t edge_off;  // lane 0: off - 8, lane 63: off + 8, other lanes: out of range
+    uint32_t ex_shift;  // where column c0-3 (lane 0) or c0+6 (lane 63) sits in the edge dword
+    bool at_start;      // c0 == 0: columns -1, -2 are mirrored
+    bool at_end;        // c0 + 4 == W: columns W, W+1 are mirrored
+};
+
 // One raw row as a lane sees it: its 4 samples and the neighbour columns.
 struct Raw {
-    int v[4];    // columns c0 .. c0+3
-    int l1, l2;  // columns c0-1, c0-2
-    int r1, r2;  // columns c0+4, c0+5
-    int ex;      // column c0-3 (lane 0) or c0+6 (lane 63), for the green beyond the wave
+    uint32_t v[4];    // columns c0 .. c0+3
+    uint32_t l1, l2;  // columns c0-1, c0-2
+    uint32_t r1, r2;  // columns c0+4, c0+5
+    uint32_t exw;     // edge lanes: column c0-3 (lane 0) or c0+6 (lane 63) in bits ex_shift..+15
 };
 
 // One green row: the lane's 4 values and the two neighbour columns.
 struct Green {
-    int g[4];
-    int gl, gr;  // columns c0-1 and c0+4
+    uint32_t g[4];
+    uint32_t gl, gr;  // columns c0-1 and c0+4
 };
 
 struct Load {
@@ -63,86 +97,90 @@ struct Load {
     uint2 edge;  // lane 0: columns c0-4 .. c0-1; lane 63: columns c0+4 .. c0+7
 };
 
-__device__ __forceinline__ Load load_row(const uint16_t* im, int W, int r, int c0, bool valid,
-                                         int lane) {
+__device__ __forceinline__ Load load_row(const uint16_t* row, uint32_t row_bytes, const Lane& ln) {
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(row, row_bytes);
     Load x;
-    x.q = make_uint2(0u, 0u);
-    x.edge = make_uint2(0u, 0u);
-    if (valid) {
-        const uint16_t* p = im + (size_t)r * (size_t)W;
-        x.q = *(const uint2*)(p + c0);
-        if (lane == 0 && c0 > 0) x.edge = *(const uint2*)(p + c0 - 4);
-        if (lane == 63 && c0 + 4 < W) x.edge = *(const uint2*)(p + c0 + 4);
-    }
+    const u32x2 q = (u32x2)__builtin_amdgcn_raw_buffer_load_b64(r, (int)ln.off, 0, 0);
+    const u32x2 e = (u32x2)__builtin_amdgcn_raw_buffer_load_b64(r, (int)ln.edge_off, 0, 0);
+    x.q = make_uint2(q.x, q.y);
+    x.edge = make_uint2(e.x, e.y);
     return x;
 }
 
-__device__ __forceinline__ Raw unpack(const Load& x, int c0, int W, int lane) {
+// EDGE: the wave holds column 0 or column W-1, so mirrored columns may be needed.
+template <bool EDGE>
+__device__ __forceinline__ Raw unpack(const Load& x, const Lane& ln) {
     Raw r;
-    r.v[0] = (int)(x.q.x & 0xffffu);
-    r.v[1] = (int)(x.q.x >> 16);
-    r.v[2] = (int)(x.q.y & 0xffffu);
-    r.v[3] = (int)(x.q.y >> 16);
-    const uint32_t left = (uint32_t)__shfl_up((int)x.q.y, 1, 64);    // c0-2 | c0-1 << 16
-    const uint32_t right = (uint32_t)__shfl_down((int)x.q.x, 1, 64); // c0+4 | c0+5 << 16
-    if (c0 == 0) {  // mirrored: -1 reads 1, -2 reads 2
-        r.l1 = r.v[1];
-        r.l2 = r.v[2];
-    } else if (lane == 0) {
-        r.l1 = (int)(x.edge.y >> 16);
-        r.l2 = (int)(x.edge.y & 0xffffu);
-    } else {
-        r.l1 = (int)(left >> 16);
-        r.l2 = (int)(left & 0xffffu);
+    r.v[0] = x.q.x & 0xffffu;
+    r.v[1] = x.q.x >> 16;
+    r.v[2] = x.q.y & 0xffffu;
+    r.v[3] = x.q.y >> 16;
+    // Columns c0-2 | c0-1 << 16 and c0+4 | c0+5 << 16: from the adjacent
+    // lanes, the edge load at the wave's edges, mirrored (2 | 1 << 16 and
+    // W-2 | W-3 << 16, both the lane's own v2 | v1 << 16) at the image's.
+    uint32_t left = from_lower_lane(x.edge.y, x.q.y);
+    uint32_t right = from_upper_lane(x.edge.x, x.q.x);
+    if (EDGE) {
+        const uint32_t mir = (x.q.y & 0xffffu) | (x.q.x & 0xffff0000u);
+        left = ln.at_start ? mir : left;
+        right = ln.at_end ? mir : right;
     }
-    if (c0 + 4 == W) {  // mirrored: W reads W-2, W+1 reads W-3
-        r.r1 = r.v[2];
-        r.r2 = r.v[1];
-    } else if (lane == 63) {
-        r.r1 = (int)(x.edge.x & 0xffffu);
-        r.r2 = (int)(x.edge.x >> 16);
-    } else {
-        r.r1 = (int)(right & 0xffffu);
-        r.r2 = (int)(right >> 16);
-    }
-    // Only lane 0 (c0 > 0) and lane 63 (c0 + 4 < W) use it.
-    r.ex = lane == 0 ? (int)(x.edge.x >> 16) : (int)(x.edge.y & 0xffffu);
+    r.l2 = left & 0xffffu;
+    r.l1 = left >> 16;
+    r.r1 = right & 0xffffu;
+    r.r2 = right >> 16;
+    r.exw = __builtin_amdgcn_alignbit(x.edge.y, x.edge.x, 16);  // c0-3 | c0-2 (lane 0), c0+5 | c0+6 (lane 63)
     return r;
 }
 
+__device__ __forceinline__ uint32_t ex_of(const Raw& r, const Lane& ln) {
+    return (r.exw >> ln.ex_shift) & 0xffffu;
+}
+
 // Column t (-1 .. 4, relative to c0) of a raw row.
-__device__ __forceinline__ int rat(const Raw& r, int t) {
+__device__ __forceinline__ uint32_t rat(const Raw& r, int t) {
     return t < 0 ? r.l1 : (t > 3 ? r.r1 : r.v[t]);
 }
 
-__device__ __forceinline__ int gat(const Green& g, int t) {
+__device__ __forceinline__ uint32_t gat(const Green& g, int t) {
     return t < 0 ? g.gl : (t > 3 ? g.gr : g.g[t]);
 }
 
-__device__ __forceinline__ int clamp16(int v) { return min(max(v, 0), 65535); }
+__device__ __forceinline__ uint32_t clamp16(int v) { return (uint32_t)min(max(v, 0), 65535); }
+
+// One of three estimates: e1 where g1 < g2, e2 where g2 < g1, their mean on a
+// tie; e1 and e2 are numerators over 2^s. Each rounds half up to
+// (2 e + 2^s) >> (s + 1), the tie to (e1 + e2 + 2^s) >> (s + 1): select
+// first, round once.
+template <int s>
+__device__ __forceinline__ uint32_t pick(uint32_t g1, uint32_t g2, int e1, int e2) {
+    const int one = g1 < g2 ? e1 : e2;
+    const int n = g1 == g2 ? e1 + e2 : 2 * one;
+    return clamp16((n + (1 << s)) >> (s + 1));
+}
 
 // Stage 1 at one R or B pixel: own sample c, green neighbours gl/gr/gu/gd,
 // same-colour samples two away cl/cr/cu/cd.
-__device__ __forceinline__ int green_at(int c, int gl, int gr, int gu, int gd, int cl, int cr,
-                                        int cu, int cd) {
-    const int lh = 2 * c - cl - cr;
-    const int lv = 2 * c - cu - cd;
-    const int dh = abs(gl - gr) + abs(lh);
-    const int dv = abs(gu - gd) + abs(lv);
-    const int eh = 2 * (gl + gr) + lh;
-    const int ev = 2 * (gu + gd) + lv;
-    const int g = dh < dv ? (eh + 2) >> 2 : (dv < dh ? (ev + 2) >> 2 : (eh + ev + 4) >> 3);
-    return clamp16(g);
+__device__ __forceinline__ uint32_t green_at(uint32_t c, uint32_t gl, uint32_t gr, uint32_t gu,
+                                             uint32_t gd, uint32_t cl, uint32_t cr, uint32_t cu,
+                                             uint32_t cd) {
+    const uint32_t c2 = 2 * c;
+    const uint32_t sh = cl + cr, sv = cu + cd;
+    const uint32_t dh = sad(gl, gr, absdiff(c2, sh));  // |Gl - Gr| + |2C - Cl - Cr|
+    const uint32_t dv = sad(gu, gd, absdiff(c2, sv));
+    const int eh = (int)(2 * (gl + gr + c)) - (int)sh;  // 2 (Gl + Gr) + 2C - Cl - Cr
+    const int ev = (int)(2 * (gu + gd + c)) - (int)sv;
+    return pick<2>(dh, dv, eh, ev);
 }
 
-// Green row rr from raw rows rr-2 .. rr+2 (u2 .. d2), with its neighbour
+// Green row from raw rows two above (u2) to two below (d2), with its neighbour
 // columns: from the adjacent lanes, mirrored at the image edges, or computed
-// by the wave's edge lanes.
-__device__ __forceinline__ Green green_row(int rr, const Raw& u2, const Raw& u1, const Raw& m,
-                                           const Raw& d1, const Raw& d2, int c0, int W,
-                                           int lane) {
+// by the wave's edge lanes. odd: a B row, non-green at odd columns (a
+// constant once the row loop is unrolled).
+template <bool EDGE>
+__device__ __forceinline__ Green green_row(bool odd, const Raw& u2, const Raw& u1, const Raw& m,
+                                           const Raw& d1, const Raw& d2, const Lane& ln) {
     Green G;
-    const bool odd = (rr & 1) != 0;  // B row: non-green at odd columns
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (((j & 1) != 0) == odd) {
@@ -156,72 +194,122 @@ __device__ __forceinline__ Green green_row(int rr, const Raw& u2, const Raw& u1,
     // The green value just beyond the wave: column c0-1 (odd, so non-green in
     // B rows) for lane 0, column c0+4 (even, non-green in R rows) for lane 63.
     // Every lane evaluates it; only the edge lanes keep the result.
-    const int extra = odd ? green_at(m.l1, m.l2, m.v[0], u1.l1, d1.l1, m.ex, m.v[1], u2.l1, d2.l1)
-                          : green_at(m.r1, m.v[3], m.r2, u1.r1, d1.r1, m.v[2], m.ex, u2.r1, d2.r1);
-    const int from_left = __shfl_up(G.g[3], 1, 64);
-    const int from_right = __shfl_down(G.g[0], 1, 64);
-    if (c0 == 0) G.gl = G.g[1];
-    else if (lane == 0) G.gl = odd ? extra : m.l1;
-    else G.gl = from_left;
-    if (c0 + 4 == W) G.gr = G.g[2];
-    else if (lane == 63) G.gr = odd ? m.r1 : extra;
-    else G.gr = from_right;
+    const uint32_t ex = ex_of(m, ln);
+    const uint32_t extra =
+        odd ? green_at(m.l1, m.l2, m.v[0], u1.l1, d1.l1, ex, m.v[1], u2.l1, d2.l1)
+            : green_at(m.r1, m.v[3], m.r2, u1.r1, d1.r1, m.v[2], ex, u2.r1, d2.r1);
+    G.gl = from_lower_lane(odd ? extra : m.l1, G.g[3]);
+    G.gr = from_upper_lane(odd ? m.r1 : extra, G.g[0]);
+    if (EDGE) {
+        G.gl = ln.at_start ? G.g[1] : G.gl;  // column -1 reads 1
+        G.gr = ln.at_end ? G.g[2] : G.gr;    // column W reads W-2
+    }
     return G;
 }
 
-// Stage 2 at one pixel: a missing colour from a pair of samples x1, x2 with
-// greens g1, g2, at a pixel with green g0.
-__device__ __forceinline__ int pair_at(int x1, int x2, int g1, int g2, int g0) {
-    return clamp16((x1 + x2 + 2 * g0 - g1 - g2 + 1) >> 1);
+// Stage 2 at a G pixel with green g0: a missing colour from the pair x1, x2
+// with greens g1, g2.
+__device__ __forceinline__ uint32_t pair_at(uint32_t x1, uint32_t x2, uint32_t g1, uint32_t g2,
+                                            uint32_t g0x2p1) {
+    return clamp16((int)(x1 + x2 + g0x2p1 - (g1 + g2)) >> 1);
 }
 
-__device__ __forceinline__ int diag_at(const Raw& u, const Raw& d, const Green& gu,
-                                       const Green& gd, int j, int g0) {
-    const int n1 = rat(u, j - 1), n2 = rat(d, j + 1);
-    const int p1 = rat(u, j + 1), p2 = rat(d, j - 1);
-    const int ln = 2 * g0 - gat(gu, j - 1) - gat(gd, j + 1);
-    const int lp = 2 * g0 - gat(gu, j + 1) - gat(gd, j - 1);
-    const int dn = abs(n1 - n2) + abs(ln);
-    const int dp = abs(p1 - p2) + abs(lp);
-    const int sn = n1 + n2 + ln, sp = p1 + p2 + lp;
-    const int v = dn < dp ? (sn + 1) >> 1 : (dp < dn ? (sp + 1) >> 1 : (sn + sp + 2) >> 2);
-    return clamp16(v);
+// Stage 2 at an R or B pixel j with green g0: the other of R and B from the
+// diagonal pair with the smaller gradient.
+__device__ __forceinline__ uint32_t diag_at(const Raw& u, const Raw& d, const Green& gu,
+                                            const Green& gd, int j, uint32_t g0) {
+    const uint32_t n1 = rat(u, j - 1), n2 = rat(d, j + 1);
+    const uint32_t p1 = rat(u, j + 1), p2 = rat(d, j - 1);
+    const uint32_t g2 = 2 * g0;
+    const uint32_t gn = gat(gu, j - 1) + gat(gd, j + 1);
+    const uint32_t gp = gat(gu, j + 1) + gat(gd, j - 1);
+    const uint32_t dn = sad(n1, n2, absdiff(g2, gn));
+    const uint32_t dp = sad(p1, p2, absdiff(g2, gp));
+    const int sn = (int)(n1 + n2 + g2) - (int)gn;
+    const int sp = (int)(p1 + p2 + g2) - (int)gp;
+    return pick<1>(dn, dp, sn, sp);
 }
 
-__device__ __forceinline__ void store_pair(uint16_t* p, const int* v) {
-    uint32_t* q = (uint32_t*)p;
-    __builtin_nontemporal_store((uint32_t)v[0] | ((uint32_t)v[1] << 16), q);
-    __builtin_nontemporal_store((uint32_t)v[2] | ((uint32_t)v[3] << 16), q + 1);
+__device__ __forceinline__ void store_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, const uint32_t* v) {
+    i32x2 w;
+    w.x = (int)(v[0] | (v[1] << 16));
+    w.y = (int)(v[2] | (v[3] << 16));
+    // Non-temporal: the planes are written once and not read back here.
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 2);
 }
 
-// Output row r from raw rows r-1, r, r+1 and green rows r-1, r, r+1.
-__device__ __forceinline__ void finish_row(int r, const Raw& u, const Raw& m, const Raw& d,
+// Output row r from raw rows r-1, r, r+1 and green rows r-1, r, r+1; `row`
+// is row r of the R plane, the G and B planes follow at `plane` samples.
+__device__ __forceinline__ void finish_row(bool red_row, const Raw& u, const Raw& m, const Raw& d,
                                            const Green& gu, const Green& gm, const Green& gd,
-                                           uint16_t* out, size_t plane, int W, int c0,
-                                           bool valid) {
-    int R[4], B[4];
-    const bool red_row = (r & 1) == 0;
+                                           uint16_t* row, size_t plane, uint32_t row_bytes,
+                                           const Lane& ln) {
+    uint32_t R[4], B[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int g0 = gm.g[j];
+        const uint32_t g0 = gm.g[j];
         const bool even = (j & 1) == 0;  // c0 is a multiple of 4
         if (red_row == even) {           // R pixel (red row) or B pixel (blue row)
-            const int other = diag_at(u, d, gu, gd, j, g0);
+            const uint32_t other = diag_at(u, d, gu, gd, j, g0);
             R[j] = red_row ? m.v[j] : other;
             B[j] = red_row ? other : m.v[j];
         } else {                         // G pixel
-            const int hor = pair_at(rat(m, j - 1), rat(m, j + 1), gat(gm, j - 1), gat(gm, j + 1), g0);
-            const int ver = pair_at(u.v[j], d.v[j], gu.g[j], gd.g[j], g0);
+            const uint32_t g0x2p1 = 2 * g0 + 1;
+            const uint32_t hor = pair_at(rat(m, j - 1), rat(m, j + 1), gat(gm, j - 1),
+                                         gat(gm, j + 1), g0x2p1);
+            const uint32_t ver = pair_at(u.v[j], d.v[j], gu.g[j], gd.g[j], g0x2p1);
             R[j] = red_row ? hor : ver;
             B[j] = red_row ? ver : hor;
         }
     }
-    if (valid) {
-        const size_t o = (size_t)r * (size_t)W + (size_t)c0;
-        // Non-temporal: the planes are written once and not read back here.
-        store_pair(out + o, R);
-        store_pair(out + plane + o, gm.g);
-        store_pair(out + 2 * plane + o, B);
+    store_nt(make_rsrc(row, row_bytes), ln.off, R);
+    store_nt(make_rsrc(row + plane, row_bytes), ln.off, gm.g);
+    store_nt(make_rsrc(row + 2 * plane, row_bytes), ln.off, B);
+}
+
+// One band of rows [r0, r1) of one image, for the wave's 256 columns.
+template <bool EDGE>
+__device__ __forceinline__ void run_band(const uint16_t* im, uint16_t* out, int H, int W, int r0,
+                                         int r1, const Lane& ln) {
+    const size_t plane = (size_t)H * (size_t)W;
+    const uint32_t row_bytes = (uint32_t)W * 2u;
+    auto row_of = [&](int rr) { return im + (size_t)mirror_index(rr, H) * (size_t)W; };
+    auto fetch = [&](int rr) { return load_row(row_of(rr), row_bytes, ln); };
+
+    // Ring slot of raw row x and green row x: (x - r0 + 1) mod 6. Six slots
+    // (five in use) and a six-fold unrolled loop: r0 and the loop step are
+    // even, so every row's colour parity is known at compile time.
+    Raw U[6];
+    Green G[6];
+    {
+        const Raw a = unpack<EDGE>(fetch(r0 - 3), ln);
+        const Raw b = unpack<EDGE>(fetch(r0 - 2), ln);
+        U[0] = unpack<EDGE>(fetch(r0 - 1), ln);
+        U[1] = unpack<EDGE>(fetch(r0), ln);
+        U[2] = unpack<EDGE>(fetch(r0 + 1), ln);
+        U[3] = unpack<EDGE>(fetch(r0 + 2), ln);
+        G[0] = green_row<EDGE>(true, a, b, U[0], U[1], U[2], ln);
+        G[1] = green_row<EDGE>(false, b, U[0], U[1], U[2], U[3], ln);
+    }
+    // Two rows in flight: L[1] holds the odd rows after r0 + 2, L[0] the even.
+    Load L[2];
+    L[1] = fetch(r0 + 3);
+    L[0] = fetch(r0 + 4);
+    for (int base = r0; base < r1; base += 6) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int r = base + k;
+            if (r >= r1) break;
+            // Raw row r+3 arrives; row r+5 is loaded while this row and the
+            // next are computed (rows beyond r1 + 2 are never needed).
+            U[(k + 4) % 6] = unpack<EDGE>(L[(k + 1) % 2], ln);
+            if (r + 3 <= r1) L[(k + 1) % 2] = fetch(r + 5);
+            const bool even = (k & 1) == 0;  // row r is an R row
+            G[(k + 2) % 6] = green_row<EDGE>(even, U[k], U[(k + 1) % 6], U[(k + 2) % 6],
+                                             U[(k + 3) % 6], U[(k + 4) % 6], ln);
+            finish_row(even, U[k], U[(k + 1) % 6], U[(k + 2) % 6], G[k], G[(k + 1) % 6],
+                       G[(k + 2) % 6], out + (size_t)r * (size_t)W, plane, row_bytes, ln);
+        }
     }
 }
 
@@ -231,7 +319,9 @@ __global__ __launch_bounds__(256) void k_demosaic_gradient(const uint16_t* __res
                                                            int32_t band, int32_t bands,
                                                            int32_t col_waves) {
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // Wave-uniform (scalar) from here: the wave index and everything derived from it.
+    const int wave =
+        __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const int per_image = bands * col_waves;
     if (wave >= images * per_image) return;  // whole waves of the last block
     const int img = wave / per_image;
@@ -239,45 +329,21 @@ __global__ __launch_bounds__(256) void k_demosaic_gradient(const uint16_t* __res
     const int bi = rem / col_waves;
     const int cw = rem - bi * col_waves;
     const int c0 = (cw * 64 + lane) * 4;
-    const bool valid = c0 < W;
+    Lane ln;
+    ln.off = (uint32_t)c0 * 2u;
+    ln.edge_off = lane == 0 ? ln.off - 8u : (lane == 63 ? ln.off + 8u : 0xfffffff0u);
+    ln.ex_shift = lane == 0 ? 0u : 16u;
+    ln.at_start = c0 == 0;
+    ln.at_end = c0 + 4 == W;
     const int r0 = bi * band;
     const int r1 = min(H, r0 + band);
     const size_t plane = (size_t)H * (size_t)W;
     const uint16_t* im = raw + (size_t)img * plane;
     uint16_t* out = rgb + (size_t)img * 3 * plane;
-
-    auto fetch = [&](int rr) {
-        return unpack(load_row(im, W, mirror_index(rr, H), c0, valid, lane), c0, W, lane);
-    };
-    // Ring slot of raw row x and green row x: (x - r0 + 1) mod 5.
-    Raw U[5];
-    Green G[5];
-    {
-        const Raw a = fetch(r0 - 3);
-        const Raw b = fetch(r0 - 2);
-        U[0] = fetch(r0 - 1);
-        U[1] = fetch(r0);
-        U[2] = fetch(r0 + 1);
-        U[3] = fetch(r0 + 2);
-        G[0] = green_row(r0 - 1, a, b, U[0], U[1], U[2], c0, W, lane);
-        G[1] = green_row(r0, b, U[0], U[1], U[2], U[3], c0, W, lane);
-    }
-    Load next = load_row(im, W, mirror_index(r0 + 3, H), c0, valid, lane);
-    for (int base = r0; base < r1; base += 5) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int r = base + k;
-            if (r >= r1) break;
-            // Raw row r+3 arrives; row r+4 is loaded while this row is computed
-            // (rows beyond r1 + 2 are never needed).
-            U[(k + 4) % 5] = unpack(next, c0, W, lane);
-            next = load_row(im, W, mirror_index(r + 4, H), c0, valid && r + 2 <= r1, lane);
-            G[(k + 2) % 5] = green_row(r + 1, U[k], U[(k + 1) % 5], U[(k + 2) % 5],
-                                       U[(k + 3) % 5], U[(k + 4) % 5], c0, W, lane);
-            finish_row(r, U[k], U[(k + 1) % 5], U[(k + 2) % 5], G[k], G[(k + 1) % 5],
-                       G[(k + 2) % 5], out, plane, W, c0, valid);
-        }
-    }
+    if (cw == 0 || cw == col_waves - 1)
+        run_band<true>(im, out, H, W, r0, r1, ln);
+    else
+        run_band<false>(im, out, H, W, r0, r1, ln);
 }
 
 }  // namespace
