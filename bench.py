@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-request batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-fit", action="store_true", help="skip the calibration-fit leg")
-    ap.add_argument("--no-demosaic", action="store_true", help="skip the demosaicing leg")
+    ap.add_argument("--no-demosaic", action="store_true", help="skip the demosaicing legs")
     ap.add_argument("--serve-jobs", type=int, default=300)
     ap.add_argument("--serve-qps", type=float, default=150.0)
     ap.add_argument("--batch-requests", type=int, default=256)
@@ -191,13 +191,16 @@ def bench_fit(args, torch, rc, dev):
     return res
 
 
-def bench_demosaic(args, torch, rc, dev):
-    """Bilinear Bayer demosaicing (the paper's case study 1): the paper's one
-    2048 x 2048 16-bit image and a batch of 16, timed on the launch stream,
-    checked bit for bit against the oracle, which is timed beside it."""
+def bench_demosaic(args, torch, rc, dev, method="bilinear"):
+    """Bayer demosaicing (the paper's case study 1), bilinear (rc_demosaic) or
+    gradient-based (rc_demosaic_gradient): the paper's one 2048 x 2048 16-bit
+    image and a batch of 16, timed on the launch stream, checked bit for bit
+    against the oracle, which is timed beside it."""
     import gen
     import oracle
     o = oracle.get()
+    call = rc.rc_demosaic if method == "bilinear" else rc.rc_demosaic_gradient
+    ref = o.demosaic if method == "bilinear" else o.demosaic_gradient
     stream = torch.cuda.Stream(device=dev)
     res = []
     for w in (0, 1):
@@ -207,24 +210,24 @@ def bench_demosaic(args, torch, rc, dev):
         out = torch.empty((images, 3, H, W), dtype=torch.int16, device=dev)
         torch.cuda.synchronize()
         for _ in range(3):
-            rc.rc_demosaic(r_t, images, H, W, out, stream)
-        reps = 50
+            call(r_t, images, H, W, out, stream)
+        reps = 200
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
-            rc.rc_demosaic(r_t, images, H, W, out, stream)
+            call(r_t, images, H, W, out, stream)
         e1.record(stream)
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / reps
         c0 = time.perf_counter()
-        want = o.demosaic(raw[:1])
+        want = ref(raw[:1])
         cpu_s = time.perf_counter() - c0
         got = out.cpu().numpy().view(np.uint16)
         exact = bool(np.array_equal(got[:1], want) and
-                     (images == 1 or np.array_equal(got[-1:], o.demosaic(raw[-1:]))))
+                     (images == 1 or np.array_equal(got[-1:], ref(raw[-1:]))))
         px = images * H * W
         nbytes = 8 * px  # 2 B read + 6 B written per pixel
-        res.append({"workload": name, "images": images, "height": H, "width": W,
+        res.append({"workload": name, "method": method, "images": images, "height": H, "width": W,
                     "demosaic_us": round(us, 2), "gpix_s": round(px / (us * 1e-6) / 1e9, 1),
                     "bytes": nbytes, "gb_s": round(nbytes / (us * 1e-6) / 1e9, 1),
                     "frac_hbm": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
@@ -534,6 +537,8 @@ def main():
 
     fit_res = None if args.no_fit else bench_fit(args, torch, rc, dev)
     demosaic_res = None if args.no_demosaic else bench_demosaic(args, torch, rc, dev)
+    gradient_res = (None if args.no_demosaic else
+                    bench_demosaic(args, torch, rc, dev, method="gradient"))
 
     batch_res = None
     del dn_t, out_t, lut_t, c_t
@@ -590,6 +595,7 @@ def main():
         },
         "fit": fit_res,
         "demosaic": demosaic_res,
+        "demosaic_gradient": gradient_res,
         "batch": batch_res,
         "serve": serve_res,
         "device": {"name": props.name, "cus": props.multi_processor_count,

@@ -417,7 +417,8 @@ void rc_host_free(void* p);
  * task on the GPU and answers with a header of the same layout followed by
  * the result. Header fields (byte offsets; text fields NUL-padded):
  *
- *   [0, 29)    task flag: "LUT_CORRECTION", "BILINEAR_DEMOSAIC", "LSQ_FIT", "GPU_INFO"
+ *   [0, 29)    task flag: "LUT_CORRECTION", "BILINEAR_DEMOSAIC", "GRADIENT_DEMOSAIC",
+ *              "LSQ_FIT", "GPU_INFO"
  *   [29]       '+' when data follows the header, '\0' when none does
  *   [30, 230)  comma-separated parameters, key=value
  *   [230, 260) output file name (the client's; echoed back, never opened here)
@@ -427,6 +428,7 @@ void rc_host_free(void* p);
  *                        out: corrected u16 [B][N][D] (then the LUT u16 [B][D][L] if lut=1)
  *     BILINEAR_DEMOSAIC  images=I,height=H,width=W
  *                        in:  raw u16 [I][H][W];  out: rgb u16 [I][3][H][W]
+ *     GRADIENT_DEMOSAIC  as BILINEAR_DEMOSAIC (rc_demosaic_gradient; height >= 4)
  *     LSQ_FIT            bands=B,points=n,detectors=D,order=m
  *                        in:  x f64 [B][n][D], then y f64 [B][n];  out: coeffs f64 [B][D][4]
  *     GPU_INFO           no parameters, no data;  out: an XML listing of the device
@@ -440,7 +442,8 @@ typedef enum {
     RC_TASK_LUT_CORRECTION = 1,
     RC_TASK_BILINEAR_DEMOSAIC = 2,
     RC_TASK_LSQ_FIT = 3,
-    RC_TASK_GPU_INFO = 4
+    RC_TASK_GPU_INFO = 4,
+    RC_TASK_GRADIENT_DEMOSAIC = 5
 } rc_task;
 
 typedef struct {

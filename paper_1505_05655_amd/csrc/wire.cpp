@@ -38,7 +38,8 @@ namespace {
 constexpr size_t kTaskLen = 29, kFlagOff = 29, kParamOff = 30, kParamLen = 200, kOutOff = 230,
                  kOutLen = 30;
 
-const char* kTaskNames[] = {nullptr, "LUT_CORRECTION", "BILINEAR_DEMOSAIC", "LSQ_FIT", "GPU_INFO"};
+const char* kTaskNames[] = {nullptr,     "LUT_CORRECTION", "BILINEAR_DEMOSAIC",
+                            "LSQ_FIT",   "GPU_INFO",       "GRADIENT_DEMOSAIC"};
 
 const char* status_name(rc_status s) {
     switch (s) {
@@ -124,7 +125,7 @@ extern "C" rc_status rc_wire_parse(const uint8_t* h, rc_wire_request* r) {
         !text_field(h, kParamOff, kParamLen, r->params) ||
         !text_field(h, kOutOff, kOutLen, r->out_name))
         return RC_EINVAL;
-    for (int t = 1; t <= 4; ++t)
+    for (int t = 1; t <= 5; ++t)
         if (std::strcmp(r->task_flag, kTaskNames[t]) == 0) r->task = t;
     if (!r->task) return RC_EINVAL;
     const uint8_t flag = h[kFlagOff];
@@ -161,10 +162,12 @@ extern "C" rc_status rc_wire_parse(const uint8_t* h, rc_wire_request* r) {
             break;
         }
         case RC_TASK_BILINEAR_DEMOSAIC:
+        case RC_TASK_GRADIENT_DEMOSAIC:
             if (!only_keys(ps, {"images", "height", "width"}) || !ps.get("images", &r->images) ||
                 !ps.get("height", &r->height) || !ps.get("width", &r->width))
                 return RC_EINVAL;
-            if (r->images < 1 || r->images > I32 || r->height < 2 || r->height > I32 ||
+            if (r->images < 1 || r->images > I32 ||
+                r->height < (r->task == RC_TASK_GRADIENT_DEMOSAIC ? 4 : 2) || r->height > I32 ||
                 r->height % 2 || r->width < 4 || r->width > I32 || r->width % 4)
                 return RC_EINVAL;
             if (!mul_u64((uint64_t)r->images, (uint64_t)r->height, &a) ||
@@ -319,6 +322,9 @@ rc_status run_device_task(const rc_wire_request& r, const uint8_t* in, uint8_t* 
         if (r.task == RC_TASK_BILINEAR_DEMOSAIC) {
             rs = rc_demosaic((const uint16_t*)d_in, (int32_t)r.images, (int32_t)r.height,
                              (int32_t)r.width, (uint16_t*)d_out, st);
+        } else if (r.task == RC_TASK_GRADIENT_DEMOSAIC) {
+            rs = rc_demosaic_gradient((const uint16_t*)d_in, (int32_t)r.images,
+                                      (int32_t)r.height, (int32_t)r.width, (uint16_t*)d_out, st);
         } else {
             const size_t xb = (size_t)(r.bands * r.points * r.detectors) * 8;
             rs = rc_fit((const double*)d_in, (const double*)((const uint8_t*)d_in + xb),

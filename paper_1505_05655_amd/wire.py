@@ -3,7 +3,8 @@ Fig. 3), and a handle on the library's TCP server.
 
 A request is a 260-byte header followed by the input data:
 
-    [0, 29)    task flag ("LUT_CORRECTION", "BILINEAR_DEMOSAIC", "LSQ_FIT", "GPU_INFO")
+    [0, 29)    task flag ("LUT_CORRECTION", "BILINEAR_DEMOSAIC", "GRADIENT_DEMOSAIC", "LSQ_FIT",
+               "GPU_INFO")
     [29]       b"+" when data follows, b"\\0" when none does
     [30, 230)  comma-separated parameters, key=value
     [230, 260) output file name
@@ -25,7 +26,7 @@ import time
 
 HEADER_BYTES = 260
 TASK_LEN, FLAG_OFF, PARAM_OFF, PARAM_LEN, OUT_OFF, OUT_LEN = 29, 29, 30, 200, 230, 30
-TASKS = ("LUT_CORRECTION", "BILINEAR_DEMOSAIC", "LSQ_FIT", "GPU_INFO")
+TASKS = ("LUT_CORRECTION", "BILINEAR_DEMOSAIC", "LSQ_FIT", "GPU_INFO", "GRADIENT_DEMOSAIC")
 
 
 def _pad(text, n, what):

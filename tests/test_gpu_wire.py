@@ -72,6 +72,11 @@ def test_demosaic_and_fit_on_one_connection(server, o):
             assert h["params"]["status"] == "RC_OK"
             rgb = np.frombuffer(res, np.uint16).reshape(1, 3, 66, 260)
             assert np.array_equal(rgb, o.demosaic(raw))
+            h, res = wire.exchange(s, "GRADIENT_DEMOSAIC", {"images": 1, "height": 66, "width": 260},
+                                   raw.tobytes(), "rgb.u16")
+            assert h["params"]["status"] == "RC_OK"
+            rgb = np.frombuffer(res, np.uint16).reshape(1, 3, 66, 260)
+            assert np.array_equal(rgb, o.demosaic_gradient(raw))
             h, res = wire.exchange(s, "LSQ_FIT", {"bands": 2, "points": 6, "detectors": 300,
                                                   "order": 2}, x.tobytes() + y.tobytes(), "c.f64")
             assert h["params"]["status"] == "RC_OK"

@@ -64,6 +64,8 @@ def test_encoder_rejects_long_fields():
      5 * 32, 5 * 2 * 2, {"lines": 0}),
     ("BILINEAR_DEMOSAIC", {"images": 2, "height": 4, "width": 8}, 2 * 4 * 8 * 2,
      2 * 3 * 4 * 8 * 2, {"images": 2, "height": 4, "width": 8}),
+    ("GRADIENT_DEMOSAIC", {"images": 1, "height": 4, "width": 4}, 4 * 4 * 2,
+     3 * 4 * 4 * 2, {"images": 1, "height": 4}),
     ("LSQ_FIT", {"bands": 3, "points": 6, "detectors": 100, "order": 2},
      3 * 6 * 100 * 8 + 3 * 6 * 8, 3 * 100 * 32, {"points": 6, "order": 2}),
 ])
@@ -108,6 +110,7 @@ def raw_header(task=b"LSQ_FIT", flag=b"+", params=b"bands=1,points=2,detectors=1
     raw_header(params=b"bands=0,points=2,detectors=1,order=1"),          # no bands
     raw_header(task=b"BILINEAR_DEMOSAIC", params=b"images=1,height=3,width=8"),   # odd height
     raw_header(task=b"BILINEAR_DEMOSAIC", params=b"images=1,height=4,width=6"),   # width % 4
+    raw_header(task=b"GRADIENT_DEMOSAIC", params=b"images=1,height=2,width=8"),   # height < 4
     raw_header(task=b"LUT_CORRECTION", params=b"bands=1,lines=1,detectors=1,levels=1"),
     raw_header(task=b"LUT_CORRECTION", params=b"bands=1,lines=1,detectors=1,levels=1024,lut=2"),
     raw_header(task=b"LUT_CORRECTION",
