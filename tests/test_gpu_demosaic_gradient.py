@@ -55,7 +55,7 @@ def test_hand_worked_images(o):
 
 SHAPES = [(1, 4, 4), (1, 4, 8), (2, 6, 12), (1, 4, 256), (1, 10, 260), (1, 64, 512),
           (3, 130, 1028), (2, 66, 4), (1, 200, 1024), (1, 34, 2048), (5, 18, 516),
-          (1, 4, 1020)]
+          (1, 4, 1020), (1, 20, 8192)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))

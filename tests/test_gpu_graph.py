@@ -1,6 +1,6 @@
 """The plain entry points allocate nothing and never synchronise, so they can
-be captured into a HIP graph. Capture fit -> LUT build -> correction and a
-demosaicing call once, then replay the graph several times with new inputs
+be captured into a HIP graph. Capture fit -> LUT build -> correction and both
+demosaicing calls once, then replay the graph several times with new inputs
 written eagerly between replays; every replay must equal the oracle."""
 import numpy as np
 import pytest
@@ -26,6 +26,7 @@ def test_graph_replays_match_oracle():
     lut = torch.empty((B, D, L), dtype=torch.int16, device=dev)
     out = torch.empty_like(dn_s)
     rgb = torch.empty((1, 3, H, W), dtype=torch.int16, device=dev)
+    rgb_g = torch.empty((1, 3, H, W), dtype=torch.int16, device=dev)
 
     def inputs(k):
         x, y = gen.calib(gen.BASE_SEED, 50, k, B, n, D, L)
@@ -41,6 +42,7 @@ def test_graph_replays_match_oracle():
         raw_s.copy_(torch.from_numpy(raw.view(np.int16)))
         out.fill_(-1)
         rgb.fill_(-1)
+        rgb_g.fill_(-1)
         torch.cuda.synchronize()
         return x, y, dn, raw
 
@@ -51,6 +53,7 @@ def test_graph_replays_match_oracle():
         rc.rc_lut_build(coeffs, B, D, L, lut, s)
         rc.rc_correct(dn_s, lut, N, D, B, L, out, s)
         rc.rc_demosaic(raw_s, 1, H, W, rgb, s)
+        rc.rc_demosaic_gradient(raw_s, 1, H, W, rgb_g, s)
 
     load(0)
     work()  # first calls set the device up outside the capture
@@ -67,3 +70,4 @@ def test_graph_replays_match_oracle():
         assert np.array_equal(coeffs.cpu().numpy().view(np.uint64), want_c.view(np.uint64)), k
         assert np.array_equal(out.cpu().numpy().view(np.uint16), want), k
         assert np.array_equal(rgb.cpu().numpy().view(np.uint16), o.demosaic(raw)), k
+        assert np.array_equal(rgb_g.cpu().numpy().view(np.uint16), o.demosaic_gradient(raw)), k
