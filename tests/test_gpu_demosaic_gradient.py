@@ -83,6 +83,20 @@ def test_edges_full_scale_and_zero(o):
     assert np.array_equal(gpu_gradient(checker), o.demosaic_gradient(checker))
 
 
+# Launches of at least 8 waves per CU with whole groups of 4 column waves
+# pass the green values beyond each wave through LDS; these take that path,
+# one with a last band of 2 rows.
+LARGE = [(16, 512, 1024), (2, 2048, 4096), (16, 530, 1024)]
+
+
+@pytest.mark.parametrize("shape", LARGE, ids=lambda s: "x".join(map(str, s)))
+def test_large_launches(o, shape):
+    rng = np.random.default_rng(sum(shape) + 11)
+    raw = smooth(rng, shape)
+    raw[:, ::7, ::5] = rng.integers(0, 65536, raw[:, ::7, ::5].shape)
+    assert np.array_equal(gpu_gradient(raw), o.demosaic_gradient(raw))
+
+
 @pytest.mark.parametrize("w", [0, 1])
 def test_demosaic_workloads(o, w):
     name, seed, cfg, images, H, W = gen.demosaic_workload(w)
