@@ -24,15 +24,17 @@
 // finishes row r. The window is a ring of six slots, and the row loop is
 // unrolled six times so the ring rotates by renaming, not by register moves,
 // and the colour parity of every row is a compile-time constant.
-// Neighbour columns come from the adjacent lanes by lane shuffles; the two
-// lanes at a wave's edge load the 4 columns beyond it instead, and compute the
-// one green value beyond the wave that stage 2 needs (at column c0-1 in B
-// rows for lane 0, c0+4 in R rows for lane 63); on large launches the four
-// waves of a workgroup hold adjacent columns and pass those values to each
-// other through LDS instead, so only the workgroup's outer waves compute
-// them. Virtual rows above and below
-// the image are computed by the same code from mirrored raw rows: the
-// stencils are symmetric, so they equal the mirrored green rows.
+// Neighbour columns come from the adjacent lanes by DPP wave shifts; the two
+// lanes at a wave's edge load the 4 columns beyond it instead, and the wave
+// computes the one green value beyond it that stage 2 needs (at column c0-1
+// in B rows for lane 0, c0+4 in R rows for lane 63). On large launches the
+// four waves of a workgroup hold adjacent columns and pass those values to
+// each other through LDS instead, so only the workgroup's outer waves compute
+// them. Virtual rows above and below the image are computed by the same code
+// from mirrored raw rows: the stencils are symmetric, so they equal the
+// mirrored green rows. Rows are read and written through buffer resources
+// that span one image row, which makes idle lanes and loads beyond the image
+// harmless (they read 0 and write nothing).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
