@@ -23,6 +23,7 @@
 #include <cerrno>
 #include <cstdio>
 #include <cstring>
+#include <list>
 #include <mutex>
 #include <new>
 #include <string>
@@ -201,6 +202,14 @@ extern "C" rc_status rc_wire_parse(const uint8_t* h, rc_wire_request* r) {
     return RC_OK;
 }
 
+// One client connection: its socket (-1 once closed), its thread, and whether
+// the thread has finished (then the acceptor joins and forgets it).
+struct rc_wire_conn {
+    int fd = -1;
+    std::atomic<bool> done{false};
+    std::thread thread;
+};
+
 struct rc_wire {
     int fd = -1;
     int port = 0;
@@ -210,8 +219,7 @@ struct rc_wire {
     std::atomic<bool> stopping{false};
     std::thread acceptor;
     std::mutex mu;
-    std::vector<std::thread> conns;
-    std::vector<int> conn_fds;
+    std::list<rc_wire_conn> conns;  // element addresses stay valid while listed
 };
 
 namespace rc {
@@ -342,7 +350,8 @@ rc_status run_device_task(const rc_wire_request& r, const uint8_t* in, uint8_t* 
     return rs;
 }
 
-void serve_connection(rc_wire* w, int fd) {
+void serve_connection(rc_wire* w, rc_wire_conn* conn) {
+    const int fd = conn->fd;
     (void)hipSetDevice(w->device);
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
@@ -402,13 +411,31 @@ void serve_connection(rc_wire* w, int fd) {
         if (!ok) break;
     }
     if (st) (void)hipStreamDestroy(st);
-    std::lock_guard<std::mutex> lk(w->mu);
-    w->conn_fds.erase(std::find(w->conn_fds.begin(), w->conn_fds.end(), fd));
-    ::close(fd);  // under the lock: rc_wire_stop never shuts down a closed descriptor
+    {
+        std::lock_guard<std::mutex> lk(w->mu);
+        ::close(fd);  // under the lock: rc_wire_stop never shuts down a closed descriptor
+        conn->fd = -1;
+    }
+    conn->done.store(true);  // last access to *conn by this thread
+}
+
+// Joins and forgets the connections whose threads have finished.
+void reap(rc_wire* w) {
+    std::list<rc_wire_conn> finished;
+    {
+        std::lock_guard<std::mutex> lk(w->mu);
+        for (auto it = w->conns.begin(); it != w->conns.end();) {
+            auto next = std::next(it);
+            if (it->done.load()) finished.splice(finished.end(), w->conns, it);
+            it = next;
+        }
+    }
+    for (auto& c : finished) c.thread.join();
 }
 
 void accept_loop(rc_wire* w) {
     while (!w->stopping.load()) {
+        reap(w);
         pollfd pfd{w->fd, POLLIN, 0};
         const int k = ::poll(&pfd, 1, 100);
         if (k <= 0 || !(pfd.revents & POLLIN)) continue;
@@ -419,11 +446,13 @@ void accept_loop(rc_wire* w) {
             ::close(c);
             break;
         }
-        w->conn_fds.push_back(c);
         try {
-            w->conns.emplace_back(serve_connection, w, c);
+            w->conns.emplace_back();
+            rc_wire_conn& conn = w->conns.back();
+            conn.fd = c;
+            conn.thread = std::thread(serve_connection, w, &conn);
         } catch (...) {
-            w->conn_fds.pop_back();
+            if (!w->conns.empty() && !w->conns.back().thread.joinable()) w->conns.pop_back();
             ::close(c);
         }
     }
@@ -490,13 +519,14 @@ void rc_wire_stop(rc_wire* w) {
     w->stopping.store(true);
     if (w->acceptor.joinable()) w->acceptor.join();
     ::close(w->fd);
-    std::vector<std::thread> conns;
+    std::list<rc_wire_conn> conns;
     {
         std::lock_guard<std::mutex> lk(w->mu);
-        for (int c : w->conn_fds) ::shutdown(c, SHUT_RDWR);  // wake blocked reads
-        conns.swap(w->conns);
+        for (auto& c : w->conns)
+            if (c.fd >= 0) ::shutdown(c.fd, SHUT_RDWR);  // wake blocked reads
+        conns.splice(conns.end(), w->conns);
     }
-    for (auto& t : conns) t.join();  // each closes its own descriptor
+    for (auto& c : conns) c.thread.join();  // each closes its own descriptor
     rc_server_destroy(w->srv);
     delete w;
 }

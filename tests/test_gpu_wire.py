@@ -101,6 +101,14 @@ def test_concurrent_clients(server, o):
         check_correction(o, params, coeffs, dn, h, res)
 
 
+def test_many_short_connections(server):
+    """Connections come and go; the server keeps answering (finished
+    connection threads are joined while it runs)."""
+    for _ in range(40):
+        h, res = wire.request("127.0.0.1", server.port, "GPU_INFO")
+        assert h["params"]["status"] == "RC_OK" and res.startswith(b"<")
+
+
 def test_malformed_header_is_refused(server):
     with socket.create_connection(("127.0.0.1", server.port), timeout=60) as s:
         s.sendall(wire.encode_header("LUT_GENERATION", "bands=1", "x", has_data=True))
