@@ -122,3 +122,49 @@ def raw_header(task=b"LSQ_FIT", flag=b"+", params=b"bands=1,points=2,detectors=1
 def test_parse_rejects(header):
     st, _ = parse(header)
     assert st == rc.RC_EINVAL
+
+
+def test_parse_random_headers():
+    """Random and mutated headers: the parser never crashes, answers only
+    RC_OK or RC_EINVAL, and an accepted header's sizes follow from its
+    parameters."""
+    import numpy as np
+    rng = np.random.default_rng(260)
+    good = [wire.encode_header("LUT_CORRECTION", {"bands": 2, "lines": 10, "detectors": 7,
+                                                  "levels": 1024}, "o", has_data=True),
+            wire.encode_header("BILINEAR_DEMOSAIC", {"images": 1, "height": 4, "width": 8}, "o",
+                               has_data=True),
+            wire.encode_header("GRADIENT_DEMOSAIC", {"images": 2, "height": 6, "width": 12}, "o",
+                               has_data=True),
+            wire.encode_header("LSQ_FIT", {"bands": 1, "points": 6, "detectors": 5, "order": 2},
+                               "o", has_data=True),
+            wire.encode_header("GPU_INFO", None, "o")]
+    accepted = 0
+    for k in range(4000):
+        if k % 4 == 0:
+            h = rng.integers(0, 256, 260, dtype=np.uint8).tobytes()
+        else:
+            h = bytearray(good[k % len(good)])
+            for _ in range(int(rng.integers(1, 4))):
+                i = int(rng.integers(0, 260))
+                h[i] = int(rng.choice([0, ord("+"), ord(","), ord("="), ord("9"), ord("0"),
+                                       ord("x"), int(rng.integers(0, 256))]))
+            h = bytes(h)
+        st, r = parse(h)
+        assert st in (rc.RC_OK, rc.RC_EINVAL)
+        if st == rc.RC_OK:
+            accepted += 1
+            task = wire.TASKS[r.task - 1]
+            if task in ("BILINEAR_DEMOSAIC", "GRADIENT_DEMOSAIC"):
+                assert r.data_bytes == r.images * r.height * r.width * 2
+                assert r.result_bytes == 3 * r.data_bytes
+            elif task == "LSQ_FIT":
+                assert r.data_bytes == r.bands * r.points * (r.detectors + 1) * 8
+                assert r.result_bytes == r.bands * r.detectors * 32
+            elif task == "LUT_CORRECTION":
+                rows = r.bands * r.detectors
+                assert r.data_bytes == rows * 32 + rows * r.lines * 2
+                assert r.result_bytes == rows * r.lines * 2 + r.want_lut * rows * r.levels * 2
+            else:
+                assert r.data_bytes == 0
+    assert accepted > 100  # many mutations keep a header valid
