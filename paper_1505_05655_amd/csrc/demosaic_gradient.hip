@@ -393,12 +393,13 @@ hipError_t launch_demosaic_gradient(const uint16_t* raw, int32_t images, int32_t
                                     uint16_t* rgb, int cus, hipStream_t stream) {
     cus = cus > 0 ? cus : 256;
     const int col_waves = (W / 4 + 63) / 64;
-    // Bands of about 16 waves per CU over the launch; at least 16 rows, since
-    // each band re-reads 5 halo rows and recomputes 2 green rows.
+    // Bands of about 16 waves per CU over the launch and at least 8 rows (each
+    // band re-reads 5 halo rows and recomputes 2 green rows; on one 2048 x 2048
+    // image 8-row bands still beat 16-row ones, which leave one wave per SIMD).
     const int64_t target = (int64_t)16 * cus;
     const int64_t col_total = (int64_t)images * col_waves;
     int64_t band = ((int64_t)H * col_total + target - 1) / target;
-    band = band < 16 ? 16 : (band > 128 ? 128 : band);
+    band = band < 8 ? 8 : (band > 128 ? 128 : band);
     band = (band + 1) & ~(int64_t)1;  // whole Bayer rows
     const int bands = (int)(((int64_t)H + band - 1) / band);
     const int64_t waves = col_total * bands;
@@ -430,8 +431,8 @@ rc_status rc_demosaic_gradient(const uint16_t* raw, int32_t images, int32_t heig
     if (!raw || !rgb) return RC_EINVAL;
     if (((uintptr_t)raw | (uintptr_t)rgb) & 7u) return RC_EINVAL;
     if (overlaps(raw, (size_t)n * 2, rgb, (size_t)n * 6)) return RC_EINVAL;
-    // Wave indices are 32-bit: images x bands x column waves < 2^31.
-    if ((int64_t)images * (height / 16 + 1) * ((width / 4 + 63) / 64) >= ((int64_t)1 << 31))
+    // Wave indices are 32-bit: images x bands x column waves < 2^31 (bands of >= 8 rows).
+    if ((int64_t)images * (height / 8 + 1) * ((width / 4 + 63) / 64) >= ((int64_t)1 << 31))
         return RC_EINVAL;
     const DeviceInfo* di = current_device();
     if (!di) return RC_EHIP;
