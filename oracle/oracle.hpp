@@ -42,7 +42,7 @@
 //   (index -1 reads 1, index H reads H-2), which keeps the colour pattern.
 //   H and W are even.
 //
-//   Gradient-based demosaicing (named in the paper's task list, §II; the method
+//   Gradient-based demosaicing (named in the paper's task list, §II, and in §III.A; the method
 //   is Hamilton & Adams' adaptive colour plane interpolation, U.S. Patent
 //   5,629,734, 1997), same filter, borders and layout, integer arithmetic:
 //   stage 1, green at R and B pixels (C = own colour, Cl2/Cr2/Cu2/Cd2 the same
@@ -62,7 +62,8 @@
 //   [0, 65535]. H and W are even and at least 4.
 //
 // Parity pins (independent of this file) live in tests/test_oracle_pins.py,
-// tests/test_oracle_fit_pins.py and tests/test_oracle_demosaic_pins.py.
+// tests/test_oracle_fit_pins.py, tests/test_oracle_demosaic_pins.py and
+// tests/test_oracle_demosaic_gradient_pins.py.
 #pragma once
 #include <stdint.h>
 
