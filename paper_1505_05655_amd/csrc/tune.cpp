@@ -65,11 +65,17 @@ std::string default_path() {
 }
 
 // Minimal reader for the flat JSON objects written by save_locked().
+// A number after "key": that converts to int32 exactly as written (the cache
+// holds integers and one timing); anything else makes the line invalid.
 bool get_num(const std::string& line, const char* key, double* out) {
     const std::string k = std::string("\"") + key + "\":";
     const size_t at = line.find(k);
     if (at == std::string::npos) return false;
-    *out = std::strtod(line.c_str() + at + k.size(), nullptr);
+    const char* begin = line.c_str() + at + k.size();
+    char* end = nullptr;
+    const double v = std::strtod(begin, &end);
+    if (end == begin || !std::isfinite(v) || v < -2147483648.0 || v > 2147483647.0) return false;
+    *out = v;
     return true;
 }
 

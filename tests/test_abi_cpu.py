@@ -219,3 +219,34 @@ def test_demosaic_gradient_rejects(args):
 def test_demosaic_gradient_empty_is_noop():
     assert L.rc_demosaic_gradient(None, 0, 4, 8, None, None) == rc.RC_OK
     assert L.rc_demosaic_gradient(None, 2, 0, 8, None, None) == rc.RC_OK
+
+
+def test_plan_cache_file_roundtrip(tmp_path):
+    """The plan cache file (host only): valid lines load, malformed ones are
+    skipped, a save reloads to the same entries, a missing file empties the
+    cache."""
+    good = ('{"arch":"gfx950","cus":256,"levels":1024,"dclass":14,"nclass":14,"bands":4,'
+            '"vmax":4,"path":2,"strip":256,"vec":4,"threads":512,"unroll":4,"chunks":1,'
+            '"xcd_remap":1,"nontemporal":2,"us":482.1}')
+    lines = [good,
+             good.replace('"levels":1024', '"levels":4096'),
+             good.replace('"strip":256,', ''),                  # missing key
+             good.replace('"cus":256', '"cus":1e300'),          # out of int range
+             good.replace('"vec":4', '"vec":nan'),              # not a number
+             good.replace('"unroll":4', '"unroll":'),           # no value
+             "garbage", ""]
+    path = tmp_path / "cache.json"
+    path.write_text("\n".join(lines) + "\n")
+    try:
+        assert rc.rc_tune_load(str(path)) == 2
+        assert rc.rc_tune_count() == 2
+        saved = tmp_path / "saved.json"
+        assert rc.rc_tune_save(str(saved)) == 2
+        assert rc.rc_tune_load(str(saved)) == 2
+        assert rc.rc_tune_load(str(tmp_path / "missing.json")) == -1
+        assert rc.rc_tune_count() == 0
+        assert rc.rc_tune_load(str(saved)) == 2
+        rc.rc_tune_clear()
+        assert rc.rc_tune_count() == 0
+    finally:
+        rc.rc_tune_load(None)  # back to the packaged cache
