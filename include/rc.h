@@ -66,7 +66,7 @@ const char* rc_status_str(rc_status s);
 int32_t rc_last_hip_error(void);
 
 /*
- * LUT build (§I: "Look-up Table (LUT) generation").
+ * LUT build (LUT generation, a task named in §I).
  *   coeffs    device, [bands][detectors][4] binary64, 8-byte aligned.
  *   levels    L in [RC_LEVELS_MIN, RC_LEVELS_MAX].
  *   lut       device, [bands][detectors][levels] uint16, 2-byte aligned; written.
@@ -78,7 +78,7 @@ rc_status rc_lut_build(const double* coeffs, int32_t bands, int32_t detectors, i
                        uint16_t* lut, hipStream_t stream);
 
 /*
- * Image correction (§I: "Image Correction") with the library's plan for this
+ * Image correction (the task §I pairs with LUT generation) with the library's plan for this
  * shape (a tuned plan from the plan cache if one matches, else the default).
  *   dn        device, [bands][lines][detectors] uint16, 2-byte aligned; read.
  *   lut       device, [bands][detectors][levels] uint16, built by rc_lut_build.

@@ -5,7 +5,7 @@
 // CPU-baseline leg may load it. It shares no source, header, table or helper
 // with the GPU library, and the GPU library never calls it.
 //
-// The paper (Banerjee & Dave, §I) names "LUT generation and image correction"
+// The paper (Banerjee & Dave, §I) names LUT generation with image correction
 // as a typical compute-heavy task but gives no formula for it. The definition
 // fixed here, and used by both sides, is:
 //

@@ -1,4 +1,4 @@
-// LUT build kernel (§I "Look-up Table (LUT) generation"): every entry of
+// LUT build kernel (LUT generation, a task named in §I): every entry of
 // lut[b][d][v] from the binary64 calibration polynomial of (b, d).
 //
 // One thread computes 8 consecutive levels of one LUT row and writes them
