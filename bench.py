@@ -508,6 +508,24 @@ def main():
         cold_a.append(e[1].elapsed_time(e[2]))
     del scratch
 
+    # Practical ceiling beside the roofline: a plain device-to-device copy of
+    # the same image (2 B read + 2 B written per pixel, no LUT) on the same
+    # stream, timed the same way.
+    cp_t = torch.empty_like(dn_t)
+    cp_ms = []
+    for i in range(23):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        with torch.cuda.stream(stream):
+            cp_t.copy_(dn_t)
+        e[1].record(stream)
+        if i >= 3:
+            cp_ms.append(e)
+    stream.synchronize()
+    cp_ms = [a.elapsed_time(b) for a, b in cp_ms]
+    del cp_t
+    copy_gbs = 4 * px / (statistics.mean(cp_ms) * 1e-3) / 1e9
+
     bit_exact = None
     cpu = None
     if not args.no_cpu_baseline or not args.no_verify:
@@ -592,6 +610,12 @@ def main():
                             "lut_build_ms_median": round(statistics.median(cold_b), 4),
                             "steps": len(cold_a),
                             "note": "512 MiB scratch write before each step"},
+            "device_copy_same_image": {
+                "ms_mean": round(statistics.mean(cp_ms), 4),
+                "ms_median": round(statistics.median(cp_ms), 4),
+                "gb_s": round(copy_gbs, 1), "frac": round(copy_gbs / HBM_PEAK_GBS, 4),
+                "lut_apply_vs_copy": round(achieved / copy_gbs, 3),
+                "note": "torch device-to-device copy of the input image, 20 launches"},
         },
         "fit": fit_res,
         "demosaic": demosaic_res,

@@ -406,9 +406,10 @@ hipError_t launch_demosaic_gradient(const uint16_t* raw, int32_t images, int32_t
     const int64_t blocks = (waves + 3) / 4;
     // The LDS exchange needs every workgroup inside one band (whole groups of
     // 4 column waves). Its barriers cost more than they save on launches of
-    // a few waves per SIMD (one 2048 x 2048 image: 11.6 vs 9.9 us), and save
-    // about 4 % on large ones (16 images: 101 vs 106 us).
-    const int exchange = (col_waves % 4 == 0 && waves >= 8 * (int64_t)cus) ? 1 : 0;
+    // up to 8 waves per CU (one 2048 x 2048 image in 8-row bands, 8 waves per
+    // CU: 9.6 vs 9.0 us), and save about 4 % on large ones (16 images: 101 vs
+    // 106 us).
+    const int exchange = (col_waves % 4 == 0 && waves > 8 * (int64_t)cus) ? 1 : 0;
     hipLaunchKernelGGL(k_demosaic_gradient, dim3((unsigned)blocks), dim3(256), 0, stream, raw, rgb,
                        images, H, W, (int)band, bands, col_waves, exchange);
     return hipGetLastError();
