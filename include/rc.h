@@ -469,7 +469,7 @@ typedef struct rc_wire rc_wire;
 typedef struct {
     int32_t port;            /* TCP port; 0 picks a free one (see rc_wire_port) */
     int32_t any_address;     /* 0: listen on 127.0.0.1 only; 1: on every interface */
-    uint64_t max_data_bytes; /* largest accepted request data; 0 = 8 GiB */
+    uint64_t max_data_bytes; /* largest accepted request data, and largest result; 0 = 8 GiB */
     uint64_t arena_bytes;    /* device arena of the internal rc_server; 0 = its default */
 } rc_wire_opts;
 

@@ -361,7 +361,11 @@ void serve_connection(rc_wire* w, rc_wire_conn* conn) {
         if (!recv_all(fd, h, sizeof h, &eof)) break;
         rc_wire_request r;
         rc_status ps = rc_wire_parse(h, &r);
-        if (ps == RC_OK && r.data_bytes > w->opts.max_data_bytes) ps = RC_ENOMEM;
+        // Both buffers are pinned host memory sized by the client's header:
+        // bound the answer too (a LUT answer can be far larger than its input).
+        if (ps == RC_OK && (r.data_bytes > w->opts.max_data_bytes ||
+                            r.result_bytes > w->opts.max_data_bytes))
+            ps = RC_ENOMEM;
         if (ps != RC_OK || !st) {
             reply(fd, h, ps != RC_OK ? ps : RC_EHIP, nullptr, 0);
             break;  // the length of the data that may follow is unknown

@@ -117,6 +117,24 @@ def test_malformed_header_is_refused(server):
         assert s.recv(1) == b""  # the server closed the connection
 
 
+def test_size_limit_covers_answers(o):
+    """max_data_bytes bounds both the data a request carries and the answer it
+    asks for (a LUT answer can be far larger than its coefficients); a refused
+    request closes its connection and the server goes on answering."""
+    with wire.WireServer(port=0, max_data_bytes=64 << 10, arena_bytes=1 << 28) as srv:
+        big_answer = {"bands": 1, "lines": 1, "detectors": 64, "levels": 4096, "lut": 1}
+        big_input = {"images": 1, "height": 256, "width": 256}
+        for task, params in (("LUT_CORRECTION", big_answer), ("BILINEAR_DEMOSAIC", big_input)):
+            with socket.create_connection(("127.0.0.1", srv.port), timeout=60) as s:
+                s.sendall(wire.encode_header(task, params, "x", has_data=True))
+                h = wire.decode_header(wire._recv_exact(s, wire.HEADER_BYTES))
+                assert h["params"]["status"] == "RC_ENOMEM" and not h["has_data"], task
+                assert s.recv(1) == b""
+        params, data, coeffs, dn = correction_case(3, B=1, N=8, D=64, L=256)
+        h, res = wire.request("127.0.0.1", srv.port, "LUT_CORRECTION", params, data, "out.u16")
+        check_correction(o, params, coeffs, dn, h, res)
+
+
 def test_stop_with_idle_connection():
     with wire.WireServer(port=0) as srv:
         s = socket.create_connection(("127.0.0.1", srv.port), timeout=60)
