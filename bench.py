@@ -615,20 +615,34 @@ def main():
         o = oracle.get()
         # The oracle is single-threaded; time whole passes of the same step
         # (LUT build + correction) until at least --cpu-seconds have elapsed.
+        # The calling thread is pinned to one core while it runs the oracle.
         want = np.empty_like(dn)
-        passes, c0 = 0, time.perf_counter()
-        while True:
-            want_lut = o.lut_build(coeffs, s.levels)
-            o.correct(dn, want_lut, out=want)
-            passes += 1
-            el = time.perf_counter() - c0
-            if args.no_cpu_baseline or el >= args.cpu_seconds:
-                break
+        affinity = os.sched_getaffinity(0)
+        core = max(affinity)
+        try:
+            os.sched_setaffinity(0, {core})
+            pinned = f"pinned to core {core}"
+        except OSError:
+            pinned = "not pinned (affinity refused)"
+        try:
+            passes, c0 = 0, time.perf_counter()
+            while True:
+                want_lut = o.lut_build(coeffs, s.levels)
+                o.correct(dn, want_lut, out=want)
+                passes += 1
+                el = time.perf_counter() - c0
+                if args.no_cpu_baseline or el >= args.cpu_seconds:
+                    break
+        finally:
+            try:
+                os.sched_setaffinity(0, affinity)
+            except OSError:
+                pass
         if not args.no_cpu_baseline:
             cpu = {"value": round(px * passes / el / 1e9, 4), "unit": "Gpix/s", "cores": 1,
                    "kind": "oracle",
                    "sample": f"{passes} full pass(es) of the same step (LUT build + correction "
-                             f"of all {px} pixels), {el:.1f}s, single-threaded, host "
+                             f"of all {px} pixels), {el:.1f}s, single-threaded, {pinned}, host "
                              f"{cpu_model()} with {os.cpu_count()} logical CPUs"}
         if not args.no_verify:
             got = out_t.cpu().numpy().view(np.uint16)
