@@ -185,13 +185,14 @@ namespace {
 
 void release(rc_batch* b) {
     if (!b) return;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->cap) hipStreamDestroy(b->cap);
-    if (b->d_reqs) hipFree(b->d_reqs);
-    if (b->d_tiles) hipFree(b->d_tiles);
-    if (b->d_prefix) hipFree(b->d_prefix);
-    if (b->d_counters) hipFree(b->d_counters);
+    // Teardown: failures here have no one left to report to.
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->d_reqs) (void)hipFree(b->d_reqs);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_prefix) (void)hipFree(b->d_prefix);
+    if (b->d_counters) (void)hipFree(b->d_counters);
     delete b;
 }
 
@@ -345,7 +346,11 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
 
     rc_batch* bt = new (std::nothrow) rc_batch();
     if (!bt) return RC_ENOMEM;
-    hipGetDevice(&bt->device);
+    const hipError_t dev_err = hipGetDevice(&bt->device);
+    if (dev_err != hipSuccess) {
+        delete bt;
+        return hip_fail(dev_err);
+    }
     bt->nreq = n;
     bt->ntiles = (int32_t)htile.size();
     bt->build_items = prefix.back();

@@ -622,17 +622,18 @@ void scheduler(rc_server* s) {
 }
 
 void release_server(rc_server* s) {
+    // Teardown: failures here have no one left to report to.
     for (Slot& sl : s->slots) {
-        if (sl.ev) hipEventDestroy(sl.ev);
-        if (sl.d_counters) hipFree(sl.d_counters);
-        if (sl.h_reqs) hipHostFree(sl.h_reqs);
-        if (sl.h_tiles) hipHostFree(sl.h_tiles);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+        if (sl.d_counters) (void)hipFree(sl.d_counters);
+        if (sl.h_reqs) (void)hipHostFree(sl.h_reqs);
+        if (sl.h_tiles) (void)hipHostFree(sl.h_tiles);
     }
-    for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
-    if (s->s_in) hipStreamDestroy(s->s_in);
-    if (s->s_comp) hipStreamDestroy(s->s_comp);
-    if (s->s_out) hipStreamDestroy(s->s_out);
-    if (s->arena_base) hipFree(s->arena_base);
+    for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+    if (s->s_in) (void)hipStreamDestroy(s->s_in);
+    if (s->s_comp) (void)hipStreamDestroy(s->s_comp);
+    if (s->s_out) (void)hipStreamDestroy(s->s_out);
+    if (s->arena_base) (void)hipFree(s->arena_base);
     delete s;
 }
 

@@ -279,7 +279,7 @@ rc_status rc_tune(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_
     if (e != hipSuccess) return hip_fail(e);
     e = hipEventCreate(&e1);
     if (e != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return hip_fail(e);
     }
     const int reps = 3;
@@ -303,8 +303,8 @@ rc_status rc_tune(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_
         }
     }
     if (e != hipSuccess) st = hip_fail(e);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != RC_OK) return st;
     if (best) *best = best_p;
     if (best_us) *best_us = best_t;
