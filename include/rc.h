@@ -240,6 +240,12 @@ rc_status rc_demosaic_gradient(const uint16_t* raw, int32_t images, int32_t heig
  * (arch, CU count, levels, ceil(log2 detectors), ceil(log2 lines), bands,
  * usable vector width). effort 0 = reduced candidate set, 1 = full sweep.
  * `best` / `best_us` (may be NULL) receive the winner and its mean time in us.
+ * Shapes whose image (4 B per pixel) and LUT take less than 512 MiB, and so
+ * would stay cached across back-to-back calls, are timed one call at a time,
+ * each after a 512 MiB scratch write that evicts the caches and a copy of the
+ * LUT that brings it back (as a preceding rc_lut_build leaves it); that
+ * scratch (512 MiB + the LUT size) is allocated for the duration of the call,
+ * and if it cannot be, such shapes are timed back to back like larger ones.
  * Synchronises `stream`; not capturable. Errors: RC_EINVAL, RC_EHIP.
  */
 rc_status rc_tune(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
