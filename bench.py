@@ -625,9 +625,11 @@ def main():
         except OSError:
             pinned = "not pinned (affinity refused)"
         try:
-            passes, c0 = 0, time.perf_counter()
+            passes, c0, build_s = 0, time.perf_counter(), 0.0
             while True:
+                b0 = time.perf_counter()
                 want_lut = o.lut_build(coeffs, s.levels)
+                build_s += time.perf_counter() - b0
                 o.correct(dn, want_lut, out=want)
                 passes += 1
                 el = time.perf_counter() - c0
@@ -641,6 +643,8 @@ def main():
         if not args.no_cpu_baseline:
             cpu = {"value": round(px * passes / el / 1e9, 4), "unit": "Gpix/s", "cores": 1,
                    "kind": "oracle",
+                   "lut_build_s": round(build_s / passes, 4),
+                   "correct_s": round((el - build_s) / passes, 4),
                    "sample": f"{passes} full pass(es) of the same step (LUT build + correction "
                              f"of all {px} pixels), {el:.1f}s, single-threaded, {pinned}, host "
                              f"{cpu_model()} with {os.cpu_count()} logical CPUs"}
