@@ -15,6 +15,12 @@ constexpr int kBatchUnroll = 4;
 constexpr size_t kBatchLds = 80 * 1024;
 // Resident workgroups per CU the batch launch aims for (2048 threads per CU).
 constexpr int kBatchPerCu = 2048 / kBatchThreads;
+// Tile queues of the persistent kernel: one per XCD (workgroups are dispatched
+// to the XCDs round-robin, so workgroup i starts on queue i % kBatchQueues).
+constexpr int kBatchQueues = 8;
+// Device counters of one launch: a head per queue, then the number of
+// workgroups that have finished.
+constexpr int kBatchCounters = kBatchQueues + 1;
 
 // Per-request descriptor, resident in device memory.
 struct BatchReq {
@@ -42,11 +48,22 @@ struct BatchTile {
     int64_t n1;
 };
 
-// Persistent correction kernel over `ntiles` tiles (grid workgroups pop
-// tiles from counters[0]; counters must be zero before the first launch and
-// are rearmed by the kernel itself).
-hipError_t launch_batch_apply(const BatchReq* reqs, const BatchTile* tiles, int32_t ntiles,
-                              unsigned int* counters, int grid, size_t lds, hipStream_t stream);
+// Queue q holds tiles [bound[q], bound[q + 1]); bound is non-decreasing from
+// 0 to the tile count. A single queue is bound = {0, n, n, ..., n}.
+struct BatchQueues {
+    int32_t bound[kBatchQueues + 1];
+};
+
+// Persistent correction kernel: each of the `grid` workgroups pops tiles
+// from its own queue, then from the others until every queue is empty.
+// `counters` holds kBatchCounters zeros before the first launch; the kernel
+// rearms them itself.
+hipError_t launch_batch_apply(const BatchReq* reqs, const BatchTile* tiles,
+                              const BatchQueues& queues, unsigned int* counters, int grid,
+                              size_t lds, hipStream_t stream);
+
+// Queues holding tiles [0, n) in one queue.
+BatchQueues single_queue(int32_t n);
 
 // Sets the persistent kernel's dynamic LDS limit on the current device.
 hipError_t prepare_batch_kernel(size_t lds);

@@ -7,13 +7,15 @@
 //     fit LDS); a thread finds its request by binary search over the prefix
 //     of work items.
 //  2. k_apply_batch: a persistent kernel (one workgroup per resident slot)
-//     whose workgroups pop tiles (request, band, strip, lines) from an atomic
-//     counter. For every other request a tile is fused: it evaluates its
+//     whose workgroups pop tiles (request, band, strip, lines) from atomic
+//     queue heads, one queue per XCD: a workgroup drains its own XCD's queue,
+//     then helps with the others. For every other request a tile is fused: it evaluates its
 //     strip's LUT rows from the coefficients straight into LDS (the first
 //     line chunk of a strip also writes them to the request's LUT), then
 //     corrects its lines, so the LUT is never read back from memory and the
 //     binary64 evaluation of one workgroup overlaps the streaming of others.
-//     Tiles are sorted longest first, so the tail of the batch is made of
+//     The strips of one request line chunk stay together on one queue,
+//     groups are dealt longest first, so the tail of the batch is made of
 //     short tiles. The last workgroup to finish resets the counters, so a
 //     replay needs no memset node.
 // Strip width, LDS mode and pixels per lane per request come from the plan
@@ -101,41 +103,56 @@ __device__ __forceinline__ void batch_tile_vec(const BatchReq& q, const BatchTil
     }
 }
 
-// counters[0]: next tile; counters[1]: workgroups finished.
+// counters[q]: next tile of queue q; counters[kBatchQueues]: workgroups finished.
 __global__ __launch_bounds__(kBatchThreads) void k_apply_batch(const BatchReq* __restrict__ reqs,
                                                                const BatchTile* __restrict__ tiles,
-                                                               int32_t ntiles,
+                                                               BatchQueues queues,
                                                                unsigned int* counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_tile;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&counters[0], 1u);
-        __syncthreads();
-        // Uniform across the workgroup: descriptor loads become scalar loads.
-        const int t = __builtin_amdgcn_readfirstlane(s_tile);
-        __syncthreads();
-        if (t >= ntiles) break;
-        const BatchTile tl = tiles[t];
-        const BatchReq q = reqs[tl.req];
-        if (q.vec == 4) batch_tile_vec<4>(q, tl, smem);
-        else if (q.vec == 2) batch_tile_vec<2>(q, tl, smem);
-        else batch_tile_vec<1>(q, tl, smem);
+    // The workgroup's own XCD queue first (neighbouring strips of one request
+    // line chunk share that XCD's L2), then whatever the other queues still hold.
+    const int home = (int)(blockIdx.x % kBatchQueues);
+    for (int k = 0; k < kBatchQueues; ++k) {
+        const int qi = (home + k) % kBatchQueues;
+        const int lo = queues.bound[qi];
+        const int n = queues.bound[qi + 1] - lo;
+        for (;;) {
+            if (threadIdx.x == 0) s_tile = (int)atomicAdd(&counters[qi], 1u);
+            __syncthreads();
+            // Uniform across the workgroup: descriptor loads become scalar loads.
+            const int t = __builtin_amdgcn_readfirstlane(s_tile);
+            __syncthreads();
+            if (t >= n) break;
+            const BatchTile tl = tiles[lo + t];
+            const BatchReq q = reqs[tl.req];
+            if (q.vec == 4) batch_tile_vec<4>(q, tl, smem);
+            else if (q.vec == 2) batch_tile_vec<2>(q, tl, smem);
+            else batch_tile_vec<1>(q, tl, smem);
+        }
     }
     if (threadIdx.x == 0) {
-        const unsigned int done = atomicAdd(&counters[1], 1u);
+        const unsigned int done = atomicAdd(&counters[kBatchQueues], 1u);
         if (done == gridDim.x - 1) {
             // Every workgroup has made its last pop: rearm for the next run.
-            atomicExch(&counters[0], 0u);
-            atomicExch(&counters[1], 0u);
+            for (int c = 0; c < kBatchCounters; ++c) atomicExch(&counters[c], 0u);
         }
     }
 }
 
-hipError_t launch_batch_apply(const BatchReq* reqs, const BatchTile* tiles, int32_t ntiles,
-                              unsigned int* counters, int grid, size_t lds, hipStream_t stream) {
+hipError_t launch_batch_apply(const BatchReq* reqs, const BatchTile* tiles,
+                              const BatchQueues& queues, unsigned int* counters, int grid,
+                              size_t lds, hipStream_t stream) {
     hipLaunchKernelGGL(k_apply_batch, dim3((unsigned)grid), dim3(kBatchThreads), lds, stream, reqs,
-                       tiles, ntiles, counters);
+                       tiles, queues, counters);
     return hipGetLastError();
+}
+
+BatchQueues single_queue(int32_t n) {
+    BatchQueues q;
+    q.bound[0] = 0;
+    for (int i = 1; i <= kBatchQueues; ++i) q.bound[i] = n;
+    return q;
 }
 
 hipError_t prepare_batch_kernel(size_t lds) {
@@ -174,6 +191,7 @@ struct rc_batch {
     BatchTile* d_tiles = nullptr;
     int64_t* d_prefix = nullptr;
     unsigned int* d_counters = nullptr;
+    BatchQueues queues{};
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -226,7 +244,7 @@ hipError_t enqueue(const rc_batch* b, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     if (b->ntiles > 0) {
-        return launch_batch_apply(b->d_reqs, b->d_tiles, b->ntiles, b->d_counters, b->slots,
+        return launch_batch_apply(b->d_reqs, b->d_tiles, b->queues, b->d_counters, b->slots,
                                   b->lds, s);
     }
     return hipSuccess;
@@ -334,15 +352,63 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
         total_lut += lut_n;
     }
     if (htile.size() > (size_t)INT32_MAX) return RC_EINVAL;
-    // Longest tiles first: image bytes of the tile plus its LUT strip (a
-    // fused tile's binary64 evaluation counted like 6 bytes per entry).
+    // Cost of a tile: image bytes of the tile plus its LUT strip (a fused
+    // tile's binary64 evaluation counted like 6 bytes per entry).
     auto cost = [&](const BatchTile& t) {
         const BatchReq& q = hreq[t.req];
         const int64_t w = std::min<int64_t>(1 << q.log_strip, q.detectors - t.d0);
         return w * ((t.n1 - t.n0) * 4 + (int64_t)q.levels * (q.fused ? 6 : 2));
     };
-    std::stable_sort(htile.begin(), htile.end(),
-                     [&](const BatchTile& a, const BatchTile& b) { return cost(a) > cost(b); });
+    // Tiles of one (request, band, line chunk) are a group: its strips hold
+    // neighbouring segments of the same lines, which share cache lines where a
+    // line's bytes do not start on a 128-byte boundary. A group goes whole to
+    // one XCD's queue, strips in order, so those lines are fetched once into
+    // that XCD's L2. Groups are dealt longest first to the least loaded queue
+    // and keep that order inside it.
+    struct Group {
+        int64_t cost = 0;
+        size_t first = 0, count = 0;
+    };
+    std::stable_sort(htile.begin(), htile.end(), [](const BatchTile& a, const BatchTile& b) {
+        if (a.req != b.req) return a.req < b.req;
+        if (a.band != b.band) return a.band < b.band;
+        if (a.n0 != b.n0) return a.n0 < b.n0;
+        return a.d0 < b.d0;
+    });
+    std::vector<Group> groups;
+    for (size_t i = 0; i < htile.size(); ++i) {
+        const BatchTile& t = htile[i];
+        if (i == 0 || t.req != htile[i - 1].req || t.band != htile[i - 1].band ||
+            t.n0 != htile[i - 1].n0) {
+            Group g;
+            g.first = i;
+            groups.push_back(g);
+        }
+        groups.back().count += 1;
+        groups.back().cost += cost(t);
+    }
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const Group& a, const Group& b) { return a.cost > b.cost; });
+    std::vector<std::vector<size_t>> qgroups(kBatchQueues);
+    int64_t qload[kBatchQueues] = {};
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        int best = 0;
+        for (int qi = 1; qi < kBatchQueues; ++qi)
+            if (qload[qi] < qload[best]) best = qi;
+        qgroups[best].push_back(gi);
+        qload[best] += groups[gi].cost;
+    }
+    std::vector<BatchTile> ordered;
+    ordered.reserve(htile.size());
+    BatchQueues queues;
+    for (int qi = 0; qi < kBatchQueues; ++qi) {
+        queues.bound[qi] = (int32_t)ordered.size();
+        for (size_t gi : qgroups[qi])
+            for (size_t k = 0; k < groups[gi].count; ++k)
+                ordered.push_back(htile[groups[gi].first + k]);
+    }
+    queues.bound[kBatchQueues] = (int32_t)ordered.size();
+    htile.swap(ordered);
 
     rc_batch* bt = new (std::nothrow) rc_batch();
     if (!bt) return RC_ENOMEM;
@@ -353,6 +419,7 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
     }
     bt->nreq = n;
     bt->ntiles = (int32_t)htile.size();
+    bt->queues = queues;
     bt->build_items = prefix.back();
     bt->lds = lds_cap;
     bt->use_graph = !(flags & RC_BATCH_NO_GRAPH);
@@ -370,7 +437,8 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
     if (!htile.empty() &&
         (e = hipMalloc(&bt->d_tiles, sizeof(BatchTile) * htile.size())) != hipSuccess)
         return fail(e);
-    if ((e = hipMalloc(&bt->d_counters, 2 * sizeof(unsigned int))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&bt->d_counters, kBatchCounters * sizeof(unsigned int))) != hipSuccess)
+        return fail(e);
     if ((e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking)) != hipSuccess)
         return fail(e);
     if (n > 0) {
@@ -385,7 +453,8 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
         (e = hipMemcpyAsync(bt->d_tiles, htile.data(), sizeof(BatchTile) * htile.size(),
                             hipMemcpyHostToDevice, bt->cap)) != hipSuccess)
         return fail(e);
-    if ((e = hipMemsetAsync(bt->d_counters, 0, 2 * sizeof(unsigned int), bt->cap)) != hipSuccess)
+    if ((e = hipMemsetAsync(bt->d_counters, 0, kBatchCounters * sizeof(unsigned int), bt->cap)) !=
+        hipSuccess)
         return fail(e);
     if ((e = hipStreamSynchronize(bt->cap)) != hipSuccess) return fail(e);
     if ((e = prepare_batch_kernel(lds_cap)) != hipSuccess) return fail(e);

@@ -440,8 +440,8 @@ bool launch_quantum(rc_server* s, hipError_t* err) {
     hipError_t e;
     // The host stores above are complete before the launch is submitted.
     std::atomic_thread_fence(std::memory_order_seq_cst);
-    if ((e = launch_batch_apply(sl.k_reqs, sl.k_tiles, nt, sl.d_counters, std::min(s->grid, nt),
-                                s->lds, s->s_comp)) != hipSuccess ||
+    if ((e = launch_batch_apply(sl.k_reqs, sl.k_tiles, single_queue(nt), sl.d_counters,
+                                std::min(s->grid, nt), s->lds, s->s_comp)) != hipSuccess ||
         (e = hipEventRecord(sl.ev, s->s_comp)) != hipSuccess) {
         *err = e;
         return false;
@@ -680,13 +680,13 @@ rc_status rc_server_create(const rc_server_opts* o, rc_server** out) {
         (e = hipStreamCreateWithFlags(&s->s_out, hipStreamNonBlocking)) != hipSuccess)
         return fail(e);
     for (Slot& sl : s->slots) {
-        if ((e = hipMalloc(&sl.d_counters, 2 * sizeof(unsigned int))) != hipSuccess ||
+        if ((e = hipMalloc(&sl.d_counters, kBatchCounters * sizeof(unsigned int))) != hipSuccess ||
             (e = hipHostMalloc((void**)&sl.h_reqs, sizeof(BatchReq) * opts.max_jobs, 0)) !=
                 hipSuccess ||
             (e = hipHostMalloc((void**)&sl.h_tiles, sizeof(BatchTile) * opts.max_quantum_tiles,
                                0)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipMemsetAsync(sl.d_counters, 0, 2 * sizeof(unsigned int), s->s_comp)) !=
+            (e = hipMemsetAsync(sl.d_counters, 0, kBatchCounters * sizeof(unsigned int), s->s_comp)) !=
                 hipSuccess ||
             (e = hipHostGetDevicePointer((void**)&sl.k_reqs, sl.h_reqs, 0)) != hipSuccess ||
             (e = hipHostGetDevicePointer((void**)&sl.k_tiles, sl.h_tiles, 0)) != hipSuccess)
