@@ -95,21 +95,39 @@ rc_status rc_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, int
 typedef enum {
     RC_PATH_LDS = 0,    /* strip LUT rows staged in LDS as 16-bit entries, level-major */
     RC_PATH_L2 = 1,     /* gathers from the global LUT, tiles ordered to stay L2-resident */
-    RC_PATH_PACKED = 2  /* strip LUT rows staged in LDS as 32-level blocks of a 16-bit base
+    RC_PATH_PACKED = 2, /* strip LUT rows staged in LDS as 32-level blocks of a 16-bit base
                            plus 2-bit steps (2.5 bits/entry, exact); a tile whose rows have a
                            step outside 0..3 gathers from the global LUT instead */
+    RC_PATH_DENSE = 3   /* strip LUT rows staged in LDS as 64-level blocks of a 16-bit header
+                           (base, slope s in 0..3) plus one bit per step (step s or s + 1),
+                           saturated runs extrapolated and clamped back (1.25 bits/entry,
+                           exact; levels <= 8192); a tile with a row that does not fit this
+                           form (decreasing, or steps spread over more than two values
+                           between unsaturated entries) gathers from the global LUT instead */
 } rc_path;
 
 typedef struct {
     int32_t path;        /* rc_path */
-    int32_t strip;       /* W: detectors per strip, power of two in [1, 1024] */
-    int32_t vec;         /* pixels per lane per line: 1, 2 or 4 */
+    int32_t strip;       /* W: widest strip, power of two in [1, 1024]; the LDS tile is sized
+                            for W detectors */
+    int32_t vec;         /* pixels per lane per line: 1, 2, 4 or 8 (8: 16-byte image accesses,
+                            needs detectors % 8 == 0 and 16-byte aligned dn and out) */
     int32_t threads;     /* workgroup size: 256, 512 or 1024 */
     int32_t unroll;      /* lines in flight per lane: 4, 8 or 16 */
     int32_t chunk_lines; /* lines per tile, >= 1 */
     int32_t xcd_remap;   /* 1: place neighbouring tiles on the same XCD */
-    int32_t nontemporal; /* image cache policy: 0 normal, 1 non-temporal loads and stores,
-                            2 non-temporal stores only */
+    int32_t nontemporal; /* image cache policy: 0 default, 1 non-temporal loads and stores,
+                            2 non-temporal stores, 3 sc0 loads + non-temporal stores,
+                            4 sc1 loads + non-temporal stores, 5 sc0 loads */
+    int32_t strips;      /* strips per band. 0: ceil(detectors / W) strips of W detectors (the
+                            last one narrower). > 0: exactly this many strips of nearly equal
+                            width (multiples of vec, each at most W), so that the tile count
+                            bands * strips * line chunks can match the device's resident
+                            workgroups: every workgroup then streams the same share of the
+                            image and stages its LUT strip once */
+    int32_t lane_map;    /* 0: W / vec lanes per strip line (a wave covers whole line segments
+                            when W / vec divides 64; lanes past a narrower strip idle);
+                            1: (strip width) / vec lanes per line, no idle lanes in a wave */
 } rc_plan;
 
 /*
@@ -128,6 +146,36 @@ rc_status rc_plan_for(int64_t lines, int32_t detectors, int32_t bands, int32_t l
 rc_status rc_correct_plan(const uint16_t* dn, const uint16_t* lut, int64_t lines,
                           int32_t detectors, int32_t bands, int32_t levels, uint16_t* out,
                           const rc_plan* plan, hipStream_t stream);
+
+/* ---- streaming ceiling: a plain device copy ------------------------------------------- */
+
+/*
+ * Launch shape of rc_stream_copy: workgroup size (256, 512 or 1024), 16-byte
+ * loads in flight per lane before the first store (2, 4 or 8), cache policy
+ * (0 default, 1 non-temporal loads and stores, 2 non-temporal stores) and
+ * resident workgroups per CU (threads * wgs_per_cu <= 2048).
+ */
+typedef struct {
+    int32_t threads;
+    int32_t unroll;
+    int32_t policy;
+    int32_t wgs_per_cu;
+} rc_copy_plan;
+
+/*
+ * Copies `bytes` bytes from src to dst on the device, with the access width
+ * (16 bytes per lane) and cache policies the correction kernels use: the
+ * practical ceiling of a stream that reads and writes the same bytes, which
+ * is what correcting an image moves apart from its LUT. Not part of the
+ * paper's task; the benchmark measures the correction against it.
+ *   src, dst  device, 16-byte aligned, not overlapping; caller-owned.
+ *   plan      NULL: 256 threads, 4 loads in flight, non-temporal, 8 per CU.
+ * Allocates nothing, never synchronises (capturable). RC_EINVAL for NULL or
+ * misaligned pointers with bytes > 0, overlap, or a plan outside the ranges
+ * above; RC_EHIP if the launch fails. bytes == 0: RC_OK, nothing enqueued.
+ */
+rc_status rc_stream_copy(const void* src, void* dst, size_t bytes, const rc_copy_plan* plan,
+                         hipStream_t stream);
 
 /* ---- least-squares calibration fit ---------------------------------------------------- */
 

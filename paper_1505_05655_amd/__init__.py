@@ -29,7 +29,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_EHIP, RC_EBUSY, RC_ECLOSED = range(6)
-RC_PATH_LDS, RC_PATH_L2, RC_PATH_PACKED = 0, 1, 2
+RC_PATH_LDS, RC_PATH_L2, RC_PATH_PACKED, RC_PATH_DENSE = 0, 1, 2, 3
 RC_NCOEF = 4
 RC_LEVELS_MIN, RC_LEVELS_MAX = 2, 65536
 
@@ -48,17 +48,30 @@ class Plan(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("strip", ctypes.c_int32), ("vec", ctypes.c_int32),
                 ("threads", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("chunk_lines", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("nontemporal", ctypes.c_int32)]
+                ("nontemporal", ctypes.c_int32), ("strips", ctypes.c_int32),
+                ("lane_map", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
     @classmethod
     def from_dict(cls, d):
-        return cls(**{k: int(d[k]) for k, _ in cls._fields_})
+        # `strips` and `lane_map` may be absent (plans written before they
+        # existed: 0, strips of W with W / vec lanes per line)
+        opt = ("strips", "lane_map")
+        return cls(**{k: int(d.get(k, 0) if k in opt else d[k]) for k, _ in cls._fields_})
 
     def __repr__(self):
         return f"Plan({self.as_dict()})"
+
+
+class CopyPlan(ctypes.Structure):
+    """Launch shape of rc_stream_copy (mirrors rc_copy_plan)."""
+    _fields_ = [("threads", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("policy", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class Request(ctypes.Structure):
@@ -166,6 +179,8 @@ _lib.rc_server_info.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 _lib.rc_server_info.restype = ctypes.c_int
 _lib.rc_server_destroy.argtypes = [_vp]
 _lib.rc_server_destroy.restype = None
+_lib.rc_stream_copy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(CopyPlan), _vp]
+_lib.rc_stream_copy.restype = ctypes.c_int
 _lib.rc_host_alloc.argtypes = [ctypes.c_size_t]
 _lib.rc_host_alloc.restype = _vp
 _lib.rc_host_free.argtypes = [_vp]
@@ -229,6 +244,13 @@ def rc_demosaic_gradient(raw, images, height, width, rgb, stream=None):
 def rc_correct(dn, lut, lines, detectors, bands, levels, out, stream=None):
     _check(_lib.rc_correct(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out),
                            _stream(stream)), "rc_correct")
+
+
+def rc_stream_copy(src, dst, nbytes, plan=None, stream=None):
+    """Plain device copy of nbytes (the streaming ceiling; see rc.h)."""
+    _check(_lib.rc_stream_copy(_ptr(src), _ptr(dst), nbytes,
+                               ctypes.byref(plan) if plan is not None else None, _stream(stream)),
+           "rc_stream_copy")
 
 
 def rc_correct_plan(dn, lut, lines, detectors, bands, levels, out, plan, stream=None):

@@ -91,9 +91,10 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 bool mul_ok(int64_t a, int64_t b, int64_t* r) { return !__builtin_mul_overflow(a, b, r); }
 
-int max_vec(const uint16_t* dn, const uint16_t* out, int32_t detectors) {
+int max_vec(const uint16_t* dn, const uint16_t* out, int32_t detectors, int cap) {
     const uintptr_t al = (uintptr_t)dn | (uintptr_t)out;
-    if (detectors % 4 == 0 && (al & 7u) == 0) return 4;
+    if (cap >= 8 && detectors % 8 == 0 && (al & 15u) == 0) return 8;
+    if (cap >= 4 && detectors % 4 == 0 && (al & 7u) == 0) return 4;
     if (detectors % 2 == 0 && (al & 3u) == 0) return 2;
     return 1;
 }
@@ -116,25 +117,27 @@ int64_t max_chunk_lines(int32_t detectors, int32_t threads, int32_t unroll) {
 size_t plan_lds_bytes(int path, int strip, int levels) {
     if (path == RC_PATH_LDS) return (size_t)strip * (size_t)levels * 2;
     if (path == RC_PATH_PACKED) return packed_lds_bytes(strip, levels);
+    if (path == RC_PATH_DENSE) return dense_lds_bytes(strip, levels);
     return 0;
 }
 
-// Default launch shape (no tuning), from measurements on MI355X. Strips are
-// made as wide as an 80 KiB LDS tile allows (two workgroups per CU), because
-// the HBM throughput of strip-shaped streams grows with the strip width:
-// packed LDS rows for L >= 512 (W = 256 at L = 1024, W = 64 at L = 4096),
-// raw 16-bit rows for smaller L, and the L2 path when fewer than 16
-// detectors would fit. Lines are split into chunks (see below) unless
-// re-staging the LUT strip per chunk would add more than a fifth to the
-// image traffic.
-void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
-                  const DeviceInfo& di, rc_plan* plan) {
+// Widest power-of-two strip (<= 1024 detectors) whose LDS tile fits `budget`.
+int widest_strip(int path, int levels, size_t budget) {
+    int W = 1024;
+    while (W > 1 && plan_lds_bytes(path, W, levels) > budget) W >>= 1;
+    return W;
+}
+
+// Legacy launch shape: power-of-two strips of W detectors, the line chunk
+// count sized for about two rounds of resident tiles. Used for the L2 path
+// (LUT rows too long for any useful LDS strip) and small scenes.
+void pow2_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
+               const DeviceInfo& di, rc_plan* plan) {
     rc_plan p;
     std::memset(&p, 0, sizeof(p));
     const size_t budget = std::min<size_t>(di.lds ? di.lds : 65536, 80 * 1024);
     const int path_lds = levels >= 512 ? RC_PATH_PACKED : RC_PATH_LDS;
-    int W = 256;
-    while (W > 1 && plan_lds_bytes(path_lds, W, levels) > budget) W >>= 1;
+    const int W = std::min(256, widest_strip(path_lds, levels, budget));
     const int64_t dcap = std::max<int64_t>(1, (int64_t)1 << (ilog2(detectors) +
                                                               (is_pow2(detectors) ? 0 : 1)));
     if (W >= 16) {
@@ -144,15 +147,12 @@ void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t level
         p.path = RC_PATH_L2;
         p.strip = (int)std::min<int64_t>(64, dcap);
     }
-    p.vec = std::min(vmax, p.strip >= 128 ? 4 : 2);
+    p.vec = std::min(std::min(vmax, 4), p.strip >= 128 ? 4 : 2);
     while (p.vec > p.strip) p.vec >>= 1;
     p.threads = 512;
     p.unroll = 8;
     p.xcd_remap = 1;
-    // Wide strips write long runs of each line: non-temporal stores pay there
-    // (measured); for narrower strips they cost more than they save.
     p.nontemporal = p.strip >= 256 ? 2 : 0;
-
     const size_t lds_bytes = plan_lds_bytes(p.path, p.strip, levels);
     const int slots = plan_slots(p, lds_bytes, di);
     const int64_t strips = (detectors + p.strip - 1) / p.strip;
@@ -179,24 +179,133 @@ void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t level
     *plan = p;
 }
 
+bool balanced_tiling(int64_t lines, int32_t detectors, int32_t bands, int vec, int wmax,
+                     int64_t target, int32_t threads, int32_t unroll, int32_t* strips_out,
+                     int32_t* strip_out, int32_t* chunk_lines_out) {
+    const int64_t units = detectors / std::max(vec, 1);
+    if (vec < 1 || wmax < vec || units < 1 || lines < 1 || bands < 1) return false;
+    target = std::max<int64_t>(1, target);
+    const int64_t per_strip = wmax / vec;                      // units per strip at most
+    const int64_t smin = (units + per_strip - 1) / per_strip;  // strips needed to fit LDS
+    const int64_t sfill = std::max<int64_t>(1, target / bands);
+    const int64_t swide = std::max<int64_t>(1, (int64_t)detectors / 64);  // >= 64 detectors
+    int64_t strips = std::max(smin, std::min(sfill, swide));
+    strips = std::min(strips, units);
+    int64_t k = std::max<int64_t>(1, target / ((int64_t)bands * strips));
+    const int64_t cap = max_chunk_lines(detectors, threads, unroll);
+    if (cap < 1) return false;
+    k = std::max(k, (lines + cap - 1) / cap);
+    k = std::min<int64_t>(k, lines);
+    const int64_t widest = vec * ((units + strips - 1) / strips);
+    int W = 1;
+    while (W < widest) W <<= 1;
+    if (strips > INT32_MAX || (lines + k - 1) / k > INT32_MAX) return false;
+    *strips_out = (int32_t)strips;
+    *strip_out = W;
+    *chunk_lines_out = (int32_t)((lines + k - 1) / k);
+    return true;
+}
+
+// Default launch shape (no tuning), from measurements on MI355X. Two tilings:
+//  - power-of-two strips of W detectors in an 80 KiB LDS tile (W = 256 for
+//    L <= 2048: 512-byte line segments), one line chunk when that already
+//    gives most CUs a tile (pow2_plan);
+//  - when the CU share of the detectors (bands x detectors / CUs) is wider
+//    than that W (long LUT rows: W = 64 at L = 4096), one tile per CU: each
+//    band cut into strips of equal width so that the tile count matches the
+//    CU count, the LUT strip in a 160 KiB tile staged once, 256 threads
+//    (one wave per SIMD, 2 pixels x 8 lines per lane and register set, no
+//    idle lanes), which keeps the fewest lines in flight per CU for the bytes
+//    it moves: more threads per CU made the L2 re-fetch the partial cache
+//    lines that neighbouring strips share (measured 1.7x the reads with 1024).
+void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
+                  const DeviceInfo& di, rc_plan* plan) {
+    rc_plan legacy;
+    pow2_plan(lines, detectors, bands, levels, vmax, di, &legacy);
+    const int64_t cus = std::max(1, di.cus);
+    const size_t cu_budget = std::min(di.lds ? di.lds : (size_t)65536,
+                                      di.lds_per_cu ? di.lds_per_cu : (size_t)65536);
+    // Long LUT rows (2048 <= L <= 8192): dense strips of up to 256 detectors
+    // (512-byte line segments) in one 160 KiB tile per CU, 512 threads, line
+    // chunks so that about one tile per CU runs.
+    const int wdense = std::min(256, widest_strip(RC_PATH_DENSE, levels, cu_budget));
+    if (levels >= 2048 && levels <= kDenseMaxLevels && wdense >= 64 && detectors >= 64) {
+        rc_plan p;
+        std::memset(&p, 0, sizeof(p));
+        p.path = RC_PATH_DENSE;
+        const int64_t dcap = (int64_t)1 << (ilog2(detectors) + (is_pow2(detectors) ? 0 : 1));
+        p.strip = (int)std::min<int64_t>(wdense, dcap);
+        p.vec = std::min(vmax, 4);
+        p.threads = 512;
+        p.unroll = 8;
+        p.xcd_remap = 1;
+        p.nontemporal = 0;
+        const int64_t strips = (detectors + p.strip - 1) / p.strip;
+        const int64_t cap = std::max<int64_t>(1, max_chunk_lines(detectors, p.threads, p.unroll));
+        int64_t k = std::max<int64_t>(1, cus / std::max<int64_t>(1, (int64_t)bands * strips));
+        k = std::max(k, (lines + cap - 1) / cap);
+        k = std::min<int64_t>(k, std::max<int64_t>(1, lines));
+        p.chunk_lines = (int32_t)std::min<int64_t>((lines + k - 1) / k, INT32_MAX);
+        *plan = p;
+        return;
+    }
+    const double share = (double)bands * (double)detectors / (double)cus;
+    if (legacy.path == RC_PATH_L2 || share <= (double)legacy.strip) {
+        *plan = legacy;
+        return;
+    }
+    const int path_lds = levels >= 512 ? RC_PATH_PACKED : RC_PATH_LDS;
+    const size_t budget = std::min(di.lds ? di.lds : (size_t)65536,
+                                   di.lds_per_cu ? di.lds_per_cu : (size_t)65536);
+    const int wmax = widest_strip(path_lds, levels, budget);
+    rc_plan p;
+    std::memset(&p, 0, sizeof(p));
+    p.path = path_lds;
+    p.vec = std::min(vmax, 2);
+    p.threads = 256;
+    p.unroll = 8;
+    p.xcd_remap = 1;
+    p.nontemporal = 0;
+    p.lane_map = 1;
+    if (wmax < 16 || !balanced_tiling(lines, detectors, bands, p.vec, wmax, cus, p.threads,
+                                      p.unroll, &p.strips, &p.strip, &p.chunk_lines)) {
+        *plan = legacy;
+        return;
+    }
+    *plan = p;
+}
+
 rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int32_t bands,
                      int32_t levels, int vmax, const DeviceInfo& di, ApplyParams* p,
                      size_t* lds_bytes) {
-    if (plan.path != RC_PATH_LDS && plan.path != RC_PATH_L2 && plan.path != RC_PATH_PACKED)
+    if (plan.path != RC_PATH_LDS && plan.path != RC_PATH_L2 && plan.path != RC_PATH_PACKED &&
+        plan.path != RC_PATH_DENSE)
         return RC_EINVAL;
+    if (plan.path == RC_PATH_DENSE && levels > kDenseMaxLevels) return RC_EINVAL;
     if (!is_pow2(plan.strip) || plan.strip > 1024) return RC_EINVAL;
-    if (plan.vec != 1 && plan.vec != 2 && plan.vec != 4) return RC_EINVAL;
+    if (plan.vec != 1 && plan.vec != 2 && plan.vec != 4 && plan.vec != 8) return RC_EINVAL;
     if (plan.vec > vmax || plan.strip < plan.vec) return RC_EINVAL;
     if (plan.threads != 256 && plan.threads != 512 && plan.threads != 1024) return RC_EINVAL;
     if (plan.unroll != 4 && plan.unroll != 8 && plan.unroll != 16) return RC_EINVAL;
+    if (plan.vec == 8 && plan.unroll != 4) return RC_EINVAL;  // would spill registers
     if (plan.chunk_lines < 1) return RC_EINVAL;
-    if (plan.nontemporal < 0 || plan.nontemporal > 2) return RC_EINVAL;
+    if (plan.nontemporal < 0 || plan.nontemporal >= kPolicies) return RC_EINVAL;
+    if (plan.lane_map < 0 || plan.lane_map > 1) return RC_EINVAL;
     if (plan.xcd_remap < 0 || plan.xcd_remap > 1) return RC_EINVAL;
     if (plan.strip / plan.vec > plan.threads) return RC_EINVAL;
     const size_t bytes = plan_lds_bytes(plan.path, plan.strip, levels);
     if (bytes > di.lds) return RC_EINVAL;
     if (plan.chunk_lines > max_chunk_lines(detectors, plan.threads, plan.unroll)) return RC_EINVAL;
-    const int64_t strips = (detectors + (int64_t)plan.strip - 1) / plan.strip;
+    if (plan.strips < 0) return RC_EINVAL;
+    int64_t strips = (detectors + (int64_t)plan.strip - 1) / plan.strip;
+    if (plan.strips > 0) {
+        // vec divides detectors (vec <= vmax); strips of whole vec units, the
+        // widest ceil(units / strips) units, at most W detectors.
+        const int64_t units = detectors / plan.vec;
+        if (plan.strips > units) return RC_EINVAL;
+        if (plan.vec * ((units + plan.strips - 1) / plan.strips) > plan.strip) return RC_EINVAL;
+        strips = plan.strips;
+    }
     const int64_t chunks = (lines + plan.chunk_lines - 1) / plan.chunk_lines;
     int64_t tiles = 0;
     if (!mul_ok((int64_t)bands * strips, chunks, &tiles)) return RC_EINVAL;
@@ -207,6 +316,9 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
     p->bands = bands;
     p->log_strip = ilog2(plan.strip);
     p->strips = (int32_t)strips;
+    p->uneven = plan.strips > 0 ? 1 : 0;
+    p->vec = plan.vec;
+    p->dense = plan.lane_map;
     p->chunks = (int32_t)chunks;
     p->chunk_lines = plan.chunk_lines;
     p->ntiles = (int32_t)tiles;
@@ -249,7 +361,7 @@ rc_status run_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, in
     if (st != RC_OK || empty) return st;
     const DeviceInfo* di = current_device();
     if (!di) return RC_EHIP;
-    const int vmax = max_vec(dn, out, detectors);
+    const int vmax = max_vec(dn, out, detectors, 8);
     rc_plan plan;
     if (forced) {
         plan = *forced;
@@ -264,7 +376,19 @@ rc_status run_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, in
     p.lut = lut;
     p.out = out;
     p.lut_vec = (levels % 8 == 0 && ((uintptr_t)lut & 15u) == 0) ? 1 : 0;
-    hipError_t e = launch_apply(p, plan, lds_bytes, stream);
+    // When the tiles fit in a few rounds of one tile per CU, cap the tiles
+    // resident per CU at ceil(tiles / CUs) through the LDS request, so the
+    // dispatcher spreads them over every CU instead of stacking two on some
+    // while others idle.
+    size_t launch_lds = lds_bytes;
+    if (plan.path != RC_PATH_L2 && di->cus > 0 && di->lds_per_cu > 0) {
+        const int64_t per = ((int64_t)p.ntiles + di->cus - 1) / di->cus;
+        if (per >= 1 && per <= 3) {
+            const size_t floor_bytes = di->lds_per_cu / (size_t)(per + 1) + 256;
+            if (floor_bytes <= di->lds) launch_lds = std::max(launch_lds, floor_bytes);
+        }
+    }
+    hipError_t e = launch_apply(p, plan, launch_lds, stream);
     return e == hipSuccess ? RC_OK : hip_fail(e);
 }
 
@@ -325,7 +449,7 @@ rc_status rc_plan_for(int64_t lines, int32_t detectors, int32_t bands, int32_t l
     if (levels < RC_LEVELS_MIN || levels > RC_LEVELS_MAX) return RC_EINVAL;
     const DeviceInfo* di = current_device();
     if (!di) return RC_EHIP;
-    const int vmax = max_vec(dn, out, detectors);
+    const int vmax = max_vec(dn, out, detectors, 8);
     const bool tuned = tuned_plan(lines, detectors, bands, levels, vmax, *di, plan);
     if (!tuned) default_plan(lines, detectors, bands, levels, vmax, *di, plan);
     if (source) *source = tuned ? 1 : 0;

@@ -99,7 +99,8 @@ __device__ __forceinline__ void batch_tile_vec(const BatchReq& q, const BatchTil
     } else {
         apply_tile<VEC, kBatchUnroll, false, kGlobal>(q.dn, q.lut, q.out, q.lines, q.detectors,
                                                       q.levels, q.log_strip, tl.band, tl.d0,
-                                                      weff, tl.n0, tl.n1, smem, q.lut_vec != 0);
+                                                      weff, tl.n0, tl.n1, smem, q.lut_vec != 0,
+                                                      false);
     }
 }
 
@@ -109,7 +110,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_apply_batch(const BatchReq* _
                                                                BatchQueues queues,
                                                                unsigned int* counters) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_tile;
+    // The popped tile index is broadcast through the first word of the tile
+    // LDS, which is dead between tiles (every tile ends with a barrier): no
+    // static LDS, so two 80 KiB workgroups fit one CU.
+    int* s_tile = (int*)smem;
     // The workgroup's own XCD queue first (neighbouring strips of one request
     // line chunk share that XCD's L2), then whatever the other queues still hold.
     const int home = (int)(blockIdx.x % kBatchQueues);
@@ -118,10 +122,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_apply_batch(const BatchReq* _
         const int lo = queues.bound[qi];
         const int n = queues.bound[qi + 1] - lo;
         for (;;) {
-            if (threadIdx.x == 0) s_tile = (int)atomicAdd(&counters[qi], 1u);
+            if (threadIdx.x == 0) *s_tile = (int)atomicAdd(&counters[qi], 1u);
             __syncthreads();
             // Uniform across the workgroup: descriptor loads become scalar loads.
-            const int t = __builtin_amdgcn_readfirstlane(s_tile);
+            const int t = __builtin_amdgcn_readfirstlane(*s_tile);
             __syncthreads();
             if (t >= n) break;
             const BatchTile tl = tiles[lo + t];
@@ -162,6 +166,7 @@ hipError_t prepare_batch_kernel(size_t lds) {
 
 void fit_request_plan(const rc_plan& plan_in, int levels, size_t lds_cap, BatchReq* q) {
     rc_plan p = plan_in;
+    if (p.vec > 4) p.vec = 4;  // the persistent kernel takes up to 4 pixels per lane
     while (p.path != RC_PATH_L2 && plan_lds_bytes(p.path, p.strip, levels) > lds_cap &&
            p.strip > p.vec)
         p.strip >>= 1;
@@ -317,7 +322,7 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
             const int64_t lines_p = std::max<int64_t>(r.lines, 1);
             rc_plan p;
             if (!tuned_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p))
-                default_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p);
+                pow2_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p);
             fit_request_plan(p, r.levels, lds_cap, &q);
             const int lw = q.log_strip;
             // One tile per (band, strip) and line chunk; strips of up to 8192

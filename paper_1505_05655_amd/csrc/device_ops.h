@@ -61,8 +61,11 @@ template <int VEC> struct Px;
 template <> struct Px<1> { typedef unsigned short T; };
 template <> struct Px<2> { typedef unsigned int T; };
 template <> struct Px<4> { typedef u32x2 T; };
+template <> struct Px<8> { typedef u32x4 T; };
 
-template <int VEC> constexpr int log_vec() { return VEC == 1 ? 0 : (VEC == 2 ? 1 : 2); }
+template <int VEC> constexpr int log_vec() {
+    return VEC == 1 ? 0 : (VEC == 2 ? 1 : (VEC == 4 ? 2 : 3));
+}
 
 // Applies f(k, dn_k) to the VEC 16-bit DNs held in w and packs the results.
 template <int VEC, typename F>
@@ -71,10 +74,17 @@ __device__ __forceinline__ typename Px<VEC>::T map_px(typename Px<VEC>::T w, F f
         return (unsigned short)f(0, (uint32_t)w);
     } else if constexpr (VEC == 2) {
         return f(0, w & 0xffffu) | (f(1, w >> 16) << 16);
-    } else {
+    } else if constexpr (VEC == 4) {
         u32x2 r;
         r.x = f(0, w.x & 0xffffu) | (f(1, w.x >> 16) << 16);
         r.y = f(2, w.y & 0xffffu) | (f(3, w.y >> 16) << 16);
+        return r;
+    } else {
+        u32x4 r;
+        r.x = f(0, w.x & 0xffffu) | (f(1, w.x >> 16) << 16);
+        r.y = f(2, w.y & 0xffffu) | (f(3, w.y >> 16) << 16);
+        r.z = f(4, w.z & 0xffffu) | (f(5, w.z >> 16) << 16);
+        r.w = f(6, w.w & 0xffffu) | (f(7, w.w >> 16) << 16);
         return r;
     }
 }
@@ -90,41 +100,65 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
 }
 
 typedef int i32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Image cache policy NT -> the cache-policy bits of the buffer loads and
+// stores (gfx950: bit 0 sc0, bit 1 nt, bit 4 sc1):
+//   0 default,  1 nt loads and stores,  2 nt stores,
+//   3 sc0 loads + nt stores,  4 sc1 loads + nt stores,  5 sc0 loads.
+constexpr int kPolicies = 6;
+constexpr int ld_aux(int nt) { return nt == 1 ? 2 : (nt == 3 || nt == 5 ? 1 : (nt == 4 ? 16 : 0)); }
+constexpr int st_aux(int nt) { return nt >= 1 && nt <= 4 ? 2 : 0; }
 
 // VEC pixels of one line through a buffer resource: per-lane byte offset
-// `vo` (VGPR) plus a wave-uniform line offset `so` (SGPR). NT selects the
-// non-temporal cache policy: 0 none, 1 loads and stores, 2 stores only.
+// `vo` (VGPR) plus a wave-uniform line offset `so` (SGPR); NT is the image
+// cache policy above.
 template <int VEC, int NT> struct Buf;
 template <int NT> struct Buf<1, NT> {
     static __device__ __forceinline__ unsigned short ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
                                                         uint32_t so) {
         return (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so,
-                                                                    NT == 1 ? 2 : 0);
+                                                                    ld_aux(NT));
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                               unsigned short v) {
-        __builtin_amdgcn_raw_buffer_store_b16((short)v, r, (int)vo, (int)so, NT != 0 ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b16((short)v, r, (int)vo, (int)so, st_aux(NT));
     }
 };
 template <int NT> struct Buf<2, NT> {
     static __device__ __forceinline__ unsigned int ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
                                                       uint32_t so) {
         return (unsigned int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so,
-                                                                  NT == 1 ? 2 : 0);
+                                                                  ld_aux(NT));
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                               unsigned int v) {
-        __builtin_amdgcn_raw_buffer_store_b32((int)v, r, (int)vo, (int)so, NT != 0 ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b32((int)v, r, (int)vo, (int)so, st_aux(NT));
     }
 };
 template <int NT> struct Buf<4, NT> {
     static __device__ __forceinline__ u32x2 ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
                                                uint32_t so) {
-        return (u32x2)__builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, NT == 1 ? 2 : 0);
+        return (u32x2)__builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, ld_aux(NT));
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                               u32x2 v) {
-        __builtin_amdgcn_raw_buffer_store_b64((i32x2)v, r, (int)vo, (int)so, NT != 0 ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b64((i32x2)v, r, (int)vo, (int)so, st_aux(NT));
+    }
+};
+template <int NT> struct Buf<8, NT> {
+    static __device__ __forceinline__ u32x4 ld(__amdgpu_buffer_rsrc_t r, uint32_t vo,
+                                               uint32_t so) {
+        return (u32x4)__builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, ld_aux(NT));
+    }
+    // A store of more than 8 bytes reads its data registers after issue; the
+    // compiler only keeps the next VALU off them when soffset is not a
+    // register (measured on gfx950: with the line offset in an SGPR, the loop
+    // counter update right after the store overwrote its first dword). The
+    // whole offset therefore goes in the VGPR, soffset is the constant 0.
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                              u32x4 v) {
+        __builtin_amdgcn_raw_buffer_store_b128((i32x4)v, r, (int)(vo + so), 0, st_aux(NT));
     }
 };
 
@@ -208,20 +242,156 @@ __host__ __device__ constexpr size_t packed_lds_bytes(int W, int L) {
     return (size_t)((L + 31) / 32) * (size_t)W * 10;
 }
 
-enum TileMode { kRaw = 0, kGlobal = 1, kPacked = 2 };
+// ---- dense LDS strip: one bit per step -------------------------------------------------
+//
+// A LUT row is cut into blocks of 64 levels. Within a block the entries
+// e_0..e_63 are stored as an unclamped staircase U_0..U_63 with
+// clamp(U_i, 0, L-1) = e_i:
+//   U_i = base + s*i + (number of t < i with bit t+1 of the plane set),
+// i.e. each step U_{t+1} - U_t is s or s + 1 (s = 0..3, the block's slope)
+// and bit t+1 of a 64-bit plane says which (bit 0 stays 0). A 16-bit header
+// holds (base << 2) | s. Where the row saturates (entries 0 before the first
+// positive one, entries L-1 from the first L-1 on) the staircase goes on
+// below 0 / above L-1 in steps of s + 1 and the clamp restores the entries.
+// For i = v mod 64:
+//   entry(v) = med3(base + s*i + popcount(plane << (63 - i)), 0, L-1),
+// exactly. 80 bits per 64 entries (1.25 bits per entry): a 4096-level strip
+// of 256 detectors fits 160 KiB. Encodable blocks: non-decreasing, with the
+// steps between unsaturated entries within {s, s+1}, s <= 3 (calibration
+// LUTs: gains near 1); other rows make the tile gather from the global LUT.
+// Layout: planes [NB][W] (64-bit) then headers [NB][W] (int16), detector j
+// of the strip at position p = (j % VEC) * (W / VEC) + j / VEC, as the packed
+// strip. Requires L <= kDenseMaxLevels = 8192 (header range).
+
+__host__ __device__ constexpr size_t dense_lds_bytes(int W, int L) {
+    return (size_t)((L + 63) / 64) * (size_t)W * 10;
+}
+
+__device__ __forceinline__ uint32_t g_dense(const uint64_t* planes, const int16_t* heads,
+                                            uint32_t dnv, uint32_t top, int logW, int p) {
+    const uint32_t v = dnv < top ? dnv : top;
+    const int idx = (int)((v >> 6) << logW) + p;
+    const uint64_t pl = planes[idx];
+    const int h = heads[idx];
+    const uint64_t sh = pl << ((~v) & 63u);  // keeps plane bits 0..i, i = v mod 64
+    const int c = __builtin_popcount((uint32_t)sh) + __builtin_popcount((uint32_t)(sh >> 32));
+    const int u = (h >> 2) + (h & 3) * (int)(v & 63u) + c;
+    return (uint32_t)min(max(u, 0), (int)top);
+}
+
+// Encodes one block of `n` entries (1..64) of a LUT row: e holds the entries
+// two per word (entry 2k in the low half of e[k]). Returns false when the
+// block is not encodable.
+__device__ __forceinline__ bool dense_encode(const uint32_t (&e)[32], int n, uint32_t top,
+                                             uint64_t* plane, int16_t* head) {
+    auto at = [&](int i) -> int { return (int)((e[i >> 1] >> ((i & 1) * 16)) & 0xffffu); };
+    // Pass 1: smallest and largest step.
+    int mn = 1 << 20, mx = -(1 << 20);
+#pragma unroll
+    for (int t = 0; t < 63; ++t) {
+        if (t + 1 < n) {
+            const int st = at(t + 1) - at(t);
+            mn = min(mn, st);
+            mx = max(mx, st);
+        }
+    }
+    if (n > 1 && mn < 0) return false;  // decreasing somewhere
+    const int e0 = at(0), elast = at(n - 1);
+    uint32_t lo = 0, hi = 0;
+    int s = 0, base = 0;
+    if (n == 1 || e0 == (int)top || elast == 0) {
+        // Constant (a single entry, all L-1, or all 0 in a non-decreasing block).
+        base = e0;
+    } else if (e0 != 0 && elast != (int)top) {
+        // No saturated entry (non-decreasing, 0 < e0, e_last < L-1).
+        s = mn;
+        if (s > 3 || mx > s + 1) return false;
+        base = e0;
+#pragma unroll
+        for (int t = 0; t < 63; ++t) {
+            if (t + 1 < n) {
+                const uint32_t b = (uint32_t)(at(t + 1) - at(t) - s);
+                if (t + 1 < 32) lo |= b << (t + 1);
+                else hi |= b << (t + 1 - 32);
+            }
+        }
+    } else {
+        // A saturation transition inside the block. Steps between two
+        // unsaturated entries (the step out of a run of 0 and into a run of
+        // L-1 included) set the slope; steps inside a saturated run are s + 1.
+        int smin = 1 << 20, smax = -(1 << 20), first = n;
+#pragma unroll
+        for (int t = 0; t < 63; ++t) {
+            if (t + 1 < n) {
+                const int a = at(t), b = at(t + 1);
+                if (b != 0 && a != (int)top) {
+                    smin = min(smin, b - a);
+                    smax = max(smax, b - a);
+                }
+                if (a == 0 && b != 0 && first == n) first = t + 1;
+            }
+        }
+        s = smin > 3 ? 4 : smin;
+        if (s > 3 || smax > s + 1) return false;
+        // U_{first-1} = 0 when the block opens with a run of 0.
+        base = e0 != 0 ? e0 : -(s + 1) * (first - 1);
+#pragma unroll
+        for (int t = 0; t < 63; ++t) {
+            if (t + 1 < n) {
+                const int a = at(t), b = at(t + 1);
+                const uint32_t bit = (b != 0 && a != (int)top) ? (uint32_t)(b - a - s) : 1u;
+                if (t + 1 < 32) lo |= bit << (t + 1);
+                else hi |= bit << (t + 1 - 32);
+            }
+        }
+    }
+    *plane = ((uint64_t)hi << 32) | lo;
+    *head = (int16_t)((base << 2) | s);
+    return true;
+}
+
+// Workgroup-wide OR of `flag` for a dense strip, in bit 0 of the first plane
+// word (a plane's bit 0 is always 0; when the flag is set the tile does not
+// decode the strip). Call after every thread has staged; every thread returns
+// the same value.
+__device__ __forceinline__ int dense_any(int flag, uint64_t* planes) {
+    __syncthreads();
+    if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr((unsigned int*)planes, 1u);
+    __syncthreads();
+    return (int)(*(const unsigned int*)planes & 1u);
+}
+
+enum TileMode { kRaw = 0, kGlobal = 1, kPacked = 2, kDense = 3 };
+
+// Workgroup-wide OR of `flag` for a packed strip, without static LDS (a
+// static word would push two 80 KiB tiles over a CU's 160 KiB). The word is
+// bit 31 of the first plane word: a block has 31 steps, so staging leaves
+// bit 31 clear and the gather masks never reach it. Call after every thread
+// has staged (planes[0] is always written: detector 0, block 0); every
+// thread returns the same value.
+__device__ __forceinline__ int packed_any(int flag, u32x2* planes) {
+    __syncthreads();
+    if (__any(flag) && (threadIdx.x & 63) == 0)
+        atomicOr((unsigned int*)planes, 0x80000000u);
+    __syncthreads();
+    return (int)(*(const unsigned int*)planes >> 31);
+}
 
 // One correction tile: band b, detectors [d0, d0 + weff), lines [n0, n1).
-// Lanes own VEC adjacent detectors of one line; W / VEC lanes cover a strip
-// line and the workgroup walks the lines. Requirements (checked on the host):
-// W = 2^logW, VEC | W, VEC | D, image pointers aligned to 2*VEC bytes,
-// W / VEC <= blockDim.x, and the LDS size of the mode. dn and out may be the
-// same buffer (in place): every pixel is read and then written by the same
-// lane, so they are deliberately not __restrict__.
+// Lanes own VEC adjacent detectors of one line; q consecutive threads cover
+// a line of the strip and the workgroup walks floor(blockDim.x / q) lines at
+// a time. q = W / VEC (`dense` false: a wave covers whole line segments when
+// q divides 64, lanes past a narrower strip idle) or weff / VEC (`dense`
+// true: no idle lanes inside a wave). Requirements (checked on the host): W = 2^logW >= weff, VEC | W,
+// VEC | weff, VEC | d0, VEC | D, image pointers aligned to 2*VEC bytes,
+// W / VEC <= blockDim.x, and the LDS size of the mode for W detectors. dn and
+// out may be the same buffer (in place): every pixel is read and then written
+// by the same lane, so they are deliberately not __restrict__.
 template <int VEC, int UNROLL, int NT, int MODE>
 __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* __restrict__ lut,
                                            uint16_t* out, int64_t N, int D, int L, int logW,
                                            int b, int d0, int weff, int64_t n0, int64_t n1,
-                                           void* smem, bool lut_vec) {
+                                           void* smem, bool lut_vec, bool dense) {
     constexpr int LOGVEC = log_vec<VEC>();
     const int W = 1 << logW;
     const int tid = threadIdx.x;
@@ -229,9 +399,13 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
     const uint32_t top = (uint32_t)(L - 1);
     const size_t Lz = (size_t)L;
     const uint16_t* strip_lut = lut + ((size_t)b * (size_t)D + (size_t)d0) * Lz;
-    const int logq = logW - LOGVEC;  // lanes per strip line = W / VEC
-    const int lane = tid & ((1 << logq) - 1);
-    const int rpp = nt >> logq;      // lines per pass
+    const int logq = logW - LOGVEC;  // LDS positions per VEC slot = W / VEC
+    const int q = dense ? (weff >> LOGVEC) : (1 << logq);  // lanes per strip line
+    const int row = tid / q;         // this thread's line within a pass
+    const int lane = tid - row * q;
+    const int rpp = nt / q;          // lines per pass
+    // Threads past the last whole line, or past the strip, only stage.
+    const bool streams = row < rpp && lane * VEC < weff;
     const int j = lane * VEC;
     // The tile's image bytes as buffer resources: line n0, detector d0 is at
     // byte 0; the range ends after the tile's last pixel.
@@ -239,7 +413,7 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
     const uint32_t span = (uint32_t)((((size_t)(n1 - n0) - 1) * (size_t)D + (size_t)weff) * 2);
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(dn + tile0, span);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + tile0, span);
-    const uint32_t vo = (uint32_t)(((size_t)(tid >> logq) * (size_t)D + (size_t)j) * 2);
+    const uint32_t vo = (uint32_t)(((size_t)row * (size_t)D + (size_t)j) * 2);
     const uint32_t line_stride = (uint32_t)rpp * (uint32_t)D * 2u;
     const int passes = (int)((n1 - n0 + (int64_t)rpp * UNROLL - 1) / ((int64_t)rpp * UNROLL));
 
@@ -289,19 +463,74 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
             }
         }
         __syncthreads();
-        if (j < weff) {
+        if (streams) {
             stream_lines<VEC, UNROLL, NT>(
                 rin, rout, vo, line_stride, passes,
                 [&](int k, uint32_t d) { return g_raw(tile, d, top, logW, j + k); });
         }
         __syncthreads();  // the tile may be restaged next
     } else if constexpr (MODE == kGlobal) {
-        if (j < weff) {
+        if (streams) {
             const uint16_t* lrow = strip_lut + (size_t)j * Lz;
             stream_lines<VEC, UNROLL, NT>(
                 rin, rout, vo, line_stride, passes,
                 [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
         }
+    } else if constexpr (MODE == kDense) {
+        const int NB = (L + 63) >> 6;
+        uint64_t* planes = (uint64_t*)smem;
+        int16_t* heads = (int16_t*)(planes + (size_t)NB * W);
+        int bad = 0;
+        // Stage: one lane encodes one block (detector jj, 64 levels); a wave
+        // covers 64 consecutive LDS positions of one block index, so its
+        // plane and header writes are consecutive words.
+        const int units = NB << logW;
+        for (int u = tid; u < units; u += nt) {
+            const int blk = u >> logW;
+            const int p = u & (W - 1);
+            const int jj = ((p & ((1 << logq) - 1)) << LOGVEC) + (p >> logq);
+            if (jj >= weff) continue;
+            const uint16_t* src = strip_lut + (size_t)jj * Lz + (size_t)blk * 64;
+            const int cnt = min(64, L - blk * 64);
+            uint32_t e[32];
+            if (lut_vec && cnt == 64) {
+#pragma unroll
+                for (int q4 = 0; q4 < 8; ++q4) {
+                    const u32x4 w = *(const u32x4*)(src + q4 * 8);
+                    e[q4 * 4 + 0] = w.x;
+                    e[q4 * 4 + 1] = w.y;
+                    e[q4 * 4 + 2] = w.z;
+                    e[q4 * 4 + 3] = w.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 32; ++k) {
+                    const uint32_t a = 2 * k < cnt ? src[2 * k] : 0u;
+                    const uint32_t b = 2 * k + 1 < cnt ? src[2 * k + 1] : 0u;
+                    e[k] = a | (b << 16);
+                }
+            }
+            uint64_t pl = 0;
+            int16_t hd = 0;
+            if (!dense_encode(e, cnt, top, &pl, &hd)) bad = 1;
+            planes[u] = pl;
+            heads[u] = hd;
+        }
+        bad = dense_any(bad, planes);
+        if (streams) {
+            if (!bad) {
+                stream_lines<VEC, UNROLL, NT>(
+                    rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
+                        return g_dense(planes, heads, d, top, logW, (k << logq) + lane);
+                    });
+            } else {
+                const uint16_t* lrow = strip_lut + (size_t)j * Lz;
+                stream_lines<VEC, UNROLL, NT>(
+                    rin, rout, vo, line_stride, passes,
+                    [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
+            }
+        }
+        __syncthreads();  // the tile may be restaged next
     } else {
         const int NB = (L + 31) >> 5;
         u32x2* planes = (u32x2*)smem;
@@ -417,8 +646,8 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
                 bases[blk * W + p] = (uint16_t)e[0];
             }
         }
-        bad = __syncthreads_or(bad);
-        if (j < weff) {
+        bad = packed_any(bad, planes);
+        if (streams) {
             if (!bad) {
                 stream_lines<VEC, UNROLL, NT>(
                     rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
@@ -546,8 +775,7 @@ __device__ __forceinline__ int build_strip(const double* __restrict__ coeffs, ui
                 }
             }
         }
-        bad = maxstep > 3u ? 1 : 0;
-        bad = __syncthreads_or(bad);
+        bad = packed_any(maxstep > 3u ? 1 : 0, planes);
     }
     return bad;
 }

@@ -8,6 +8,9 @@
 
 namespace rc {
 
+// Longest LUT rows the dense LDS strip encodes (16-bit block headers).
+constexpr int kDenseMaxLevels = 8192;
+
 // Everything the correction kernel needs to decode a tile id.
 struct ApplyParams {
     const uint16_t* dn;
@@ -17,8 +20,12 @@ struct ApplyParams {
     int32_t detectors;   // D
     int32_t levels;      // L
     int32_t bands;       // B
-    int32_t log_strip;   // log2(W)
-    int32_t strips;      // ceil(D / W)
+    int32_t log_strip;   // log2(W): LDS tile width, widest strip
+    int32_t strips;      // strips per band: ceil(D / W), or the plan's count when uneven
+    int32_t uneven;      // 1: strip s is detector units [s*U/strips, (s+1)*U/strips) with
+                         //    U = D / vec (units of vec detectors); 0: strip s is [s*W, s*W+W)
+    int32_t vec;         // pixels per lane (the unit of uneven strips)
+    int32_t dense;       // lanes per strip line: 0 W / vec, 1 strip width / vec
     int32_t chunks;      // ceil(N / chunk_lines)
     int64_t chunk_lines;
     int32_t ntiles;      // bands * strips * chunks

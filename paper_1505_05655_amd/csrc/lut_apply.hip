@@ -27,37 +27,57 @@ __global__ __launch_bounds__(1024) void k_apply(ApplyParams p) {
         c = r % p.chunks;
         b = r / p.chunks;
     }
-    const int W = 1 << p.log_strip;
-    const int d0 = s * W;
-    const int weff = min(W, p.detectors - d0);
+    int d0, weff;
+    if (p.uneven) {
+        const int64_t units = p.detectors / p.vec;
+        const int u0 = (int)((int64_t)s * units / p.strips);
+        const int u1 = (int)((int64_t)(s + 1) * units / p.strips);
+        d0 = u0 * p.vec;
+        weff = (u1 - u0) * p.vec;
+    } else {
+        const int W = 1 << p.log_strip;
+        d0 = s * W;
+        weff = min(W, p.detectors - d0);
+    }
     const int64_t n0 = (int64_t)c * p.chunk_lines;
     const int64_t n1 = min(p.lines, n0 + p.chunk_lines);
     apply_tile<VEC, UNROLL, NT, MODE>(p.dn, p.lut, p.out, p.lines, p.detectors, p.levels,
-                                       p.log_strip, b, d0, weff, n0, n1, smem, p.lut_vec != 0);
+                                       p.log_strip, b, d0, weff, n0, n1, smem, p.lut_vec != 0,
+                                       p.dense != 0);
 }
 
 typedef void (*ApplyKernel)(ApplyParams);
 
 namespace {
 
-// row[nontemporal * 3 + mode], mode = rc_path value (raw LDS, L2, packed LDS),
-// nontemporal = 0 (none), 1 (loads and stores), 2 (stores only)
-template <int VEC, int UNROLL>
-void fill_row(ApplyKernel* row) {
-    row[0] = k_apply<VEC, UNROLL, 0, kRaw>;
-    row[1] = k_apply<VEC, UNROLL, 0, kGlobal>;
-    row[2] = k_apply<VEC, UNROLL, 0, kPacked>;
-    row[3] = k_apply<VEC, UNROLL, 1, kRaw>;
-    row[4] = k_apply<VEC, UNROLL, 1, kGlobal>;
-    row[5] = k_apply<VEC, UNROLL, 1, kPacked>;
-    row[6] = k_apply<VEC, UNROLL, 2, kRaw>;
-    row[7] = k_apply<VEC, UNROLL, 2, kGlobal>;
-    row[8] = k_apply<VEC, UNROLL, 2, kPacked>;
+// row[policy * kModes + mode], mode = rc_path value (raw LDS, L2, packed
+// LDS, dense LDS), policy = the plan's image cache policy (0..kPolicies-1)
+constexpr int kModes = 4;
+
+template <int VEC, int UNROLL, int NT>
+void fill_policy(ApplyKernel* row) {
+    row[NT * kModes + 0] = k_apply<VEC, UNROLL, NT, kRaw>;
+    row[NT * kModes + 1] = k_apply<VEC, UNROLL, NT, kGlobal>;
+    row[NT * kModes + 2] = k_apply<VEC, UNROLL, NT, kPacked>;
+    row[NT * kModes + 3] = k_apply<VEC, UNROLL, NT, kDense>;
 }
 
-// table[vec index][unroll index][nontemporal * 3 + mode]
+template <int VEC, int UNROLL>
+void fill_row(ApplyKernel* row) {
+    fill_policy<VEC, UNROLL, 0>(row);
+    fill_policy<VEC, UNROLL, 1>(row);
+    fill_policy<VEC, UNROLL, 2>(row);
+    fill_policy<VEC, UNROLL, 3>(row);
+    fill_policy<VEC, UNROLL, 4>(row);
+    fill_policy<VEC, UNROLL, 5>(row);
+    static_assert(kPolicies == 6, "one fill_policy per cache policy");
+}
+
+constexpr int kRow = kPolicies * kModes;
+
+// table[vec index][unroll index][policy * kModes + mode]
 struct Table {
-    ApplyKernel k[3][3][9];
+    ApplyKernel k[4][3][kRow];
     Table() {
         fill_row<1, 4>(k[0][0]);
         fill_row<1, 8>(k[0][1]);
@@ -68,6 +88,11 @@ struct Table {
         fill_row<4, 4>(k[2][0]);
         fill_row<4, 8>(k[2][1]);
         fill_row<4, 16>(k[2][2]);
+        fill_row<8, 4>(k[3][0]);
+        // 8 pixels x 8 or 16 lines per register set spill registers: not
+        // built, and check_plan rejects them (8 x 4 holds as many pixels per
+        // set as 4 x 8).
+        for (int m = 0; m < kRow; ++m) k[3][1][m] = k[3][2][m] = nullptr;
     }
 };
 
@@ -76,7 +101,7 @@ const Table& table() {
     return t;
 }
 
-int vec_index(int vec) { return vec == 1 ? 0 : (vec == 2 ? 1 : 2); }
+int vec_index(int vec) { return vec == 1 ? 0 : (vec == 2 ? 1 : (vec == 4 ? 2 : 3)); }
 int unroll_index(int u) { return u == 4 ? 0 : (u == 8 ? 1 : 2); }
 
 }  // namespace
@@ -86,10 +111,10 @@ hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
     // (e.g. the word __syncthreads_or reduces through).
     const Table& t = table();
     size_t worst_static = 0;
-    for (int v = 0; v < 3; ++v)
+    for (int v = 0; v < 4; ++v)
         for (int u = 0; u < 3; ++u)
-            for (int m = 0; m < 9; ++m) {
-                if (m % 3 == kGlobal) continue;
+            for (int m = 0; m < kRow; ++m) {
+                if (m % kModes == kGlobal || !t.k[v][u][m]) continue;
                 hipFuncAttributes attr;
                 hipError_t e = hipFuncGetAttributes(&attr, (const void*)t.k[v][u][m]);
                 if (e != hipSuccess) return e;
@@ -97,10 +122,10 @@ hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
                                                                    : worst_static;
             }
     const size_t dyn = bytes > worst_static ? bytes - worst_static : 0;
-    for (int v = 0; v < 3; ++v)
+    for (int v = 0; v < 4; ++v)
         for (int u = 0; u < 3; ++u)
-            for (int m = 0; m < 9; ++m) {
-                if (m % 3 == kGlobal) continue;
+            for (int m = 0; m < kRow; ++m) {
+                if (m % kModes == kGlobal || !t.k[v][u][m]) continue;
                 hipError_t e = hipFuncSetAttribute((const void*)t.k[v][u][m],
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    (int)dyn);
@@ -113,7 +138,8 @@ hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
 hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,
                         hipStream_t stream) {
     ApplyKernel k = table().k[vec_index(plan.vec)][unroll_index(plan.unroll)]
-                             [plan.nontemporal * 3 + plan.path];
+                             [plan.nontemporal * kModes + plan.path];
+    if (!k) return hipErrorInvalidValue;  // combinations check_plan rejects
     hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3((unsigned)plan.threads),
                        plan.path == RC_PATH_L2 ? 0 : lds_bytes, stream, p);
     return hipGetLastError();

@@ -28,8 +28,27 @@ const DeviceInfo* current_device(int* dev_out = nullptr);
 // Records `e` as this thread's last HIP error and returns RC_EHIP.
 rc_status hip_fail(hipError_t e);
 
-// Largest VEC the image pointers and the detector count allow (1, 2 or 4).
-int max_vec(const uint16_t* dn, const uint16_t* out, int32_t detectors);
+// Largest VEC (1, 2, 4, or 8 when cap >= 8) the image pointers and the
+// detector count allow. The plain correction kernels take up to 8 pixels per
+// lane, the persistent batch kernel up to 4.
+int max_vec(const uint16_t* dn, const uint16_t* out, int32_t detectors, int cap = 4);
+
+// Launch shape with power-of-two strips of W detectors and about two rounds
+// of resident tiles (the persistent batch and serving kernels tile requests
+// this way; the plain path uses it for the L2 path).
+void pow2_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
+               const DeviceInfo& di, rc_plan* plan);
+
+// Strips per band, strip bound W (power of two) and line chunk for about
+// `target` equal tiles: strips of at least 64 detectors (or as many as fit
+// `wmax`, the widest strip the LDS tile allows), whole units of `vec`
+// detectors, then line chunks to reach the target. False if no tiling fits.
+bool balanced_tiling(int64_t lines, int32_t detectors, int32_t bands, int vec, int wmax,
+                     int64_t target, int32_t threads, int32_t unroll, int32_t* strips,
+                     int32_t* strip, int32_t* chunk_lines);
+
+// Widest power-of-two strip (<= 1024 detectors) whose LDS tile fits `budget`.
+int widest_strip(int path, int levels, size_t budget);
 
 // Default launch shape for a shape class (no tuning).
 void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,

@@ -280,7 +280,7 @@ hipError_t admit(rc_server* s, const std::shared_ptr<Job>& jp) {
         const int64_t lines_p = std::max<int64_t>(h.lines, 1);
         rc_plan p;
         if (!tuned_plan(lines_p, h.detectors, h.bands, h.levels, vmax, *s->di, &p))
-            default_plan(lines_p, h.detectors, h.bands, h.levels, vmax, *s->di, &p);
+            pow2_plan(lines_p, h.detectors, h.bands, h.levels, vmax, *s->di, &p);
         fit_request_plan(p, h.levels, s->lds, &q);
     }
     // Pieces: per band, runs of lines of about piece_pixels pixels.

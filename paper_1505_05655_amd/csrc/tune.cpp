@@ -111,6 +111,11 @@ bool parse_entry(const std::string& line, Entry* e) {
     e->plan.xcd_remap = (int32_t)v[12];
     e->plan.nontemporal = (int32_t)v[13];
     e->us = v[14];
+    // Entries written before uneven strips existed have no "strips" key: 0.
+    double st = 0.0;
+    e->plan.strips = get_num(line, "strips", &st) ? (int32_t)st : 0;
+    e->plan.lane_map = get_num(line, "lane_map", &st) ? (int32_t)st : 0;
+    if (e->plan.strips < 0) return false;
     return true;
 }
 
@@ -143,10 +148,11 @@ int save_locked(const std::string& path) {
                      "{\"arch\":\"%s\",\"cus\":%d,\"levels\":%d,\"dclass\":%d,\"nclass\":%d,"
                      "\"bands\":%d,\"vmax\":%d,\"path\":%d,\"strip\":%d,\"vec\":%d,"
                      "\"threads\":%d,\"unroll\":%d,\"chunks\":%d,\"xcd_remap\":%d,"
-                     "\"nontemporal\":%d,\"us\":%.3f}\n",
+                     "\"nontemporal\":%d,\"strips\":%d,\"lane_map\":%d,\"us\":%.3f}\n",
                      e.arch.c_str(), e.cus, e.levels, e.dclass, e.nclass, e.bands, e.vmax,
                      e.plan.path, e.plan.strip, e.plan.vec, e.plan.threads, e.plan.unroll,
-                     e.chunks, e.plan.xcd_remap, e.plan.nontemporal, e.us);
+                     e.chunks, e.plan.xcd_remap, e.plan.nontemporal, e.plan.strips,
+                     e.plan.lane_map, e.us);
     }
     const bool ok = std::fclose(f) == 0;
     if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) return -1;
@@ -224,11 +230,53 @@ std::vector<rc_plan> candidates(int64_t lines, int32_t detectors, int32_t bands,
         p.chunk_lines = (int32_t)((lines + k - 1) / k);
         out.push_back(p);
     };
+    // Balanced tilings: one tile per resident workgroup (1 or 2 per CU), or
+    // two rounds of them; pixels per lane up to 8 (16-byte accesses).
+    {
+        std::vector<int> vecs8;
+        for (int v = std::min(vmax, 8); v >= 1 && vecs8.size() < (effort ? 3u : 2u); v >>= 1)
+            vecs8.push_back(v);
+        const int cus = std::max(1, di.cus);
+        for (int path : {RC_PATH_PACKED, RC_PATH_LDS})
+            for (int per_cu : {1, 2}) {
+                const size_t budget =
+                    std::min(di.lds, (di.lds_per_cu ? di.lds_per_cu : di.lds) / per_cu);
+                const int wmax = widest_strip(path, levels, budget);
+                if (wmax < 16) continue;
+                for (int threads : {256, 512, 1024}) {
+                    if (threads * per_cu > 2048) continue;
+                    for (int vec : vecs8)
+                        for (int unroll : {4, 8})
+                            for (int nt : {0, 2})
+                                for (int rounds : {1, 2})
+                                    for (int lane_map : {0, 1}) {
+                                        if (vec == 8 && unroll != 4) continue;
+                                        rc_plan p;
+                                        std::memset(&p, 0, sizeof p);
+                                        p.path = path;
+                                        p.vec = vec;
+                                        p.threads = threads;
+                                        p.unroll = unroll;
+                                        p.xcd_remap = 1;
+                                        p.nontemporal = nt;
+                                        p.lane_map = lane_map;
+                                        if (!balanced_tiling(lines, detectors, bands, vec, wmax,
+                                                             (int64_t)per_cu * cus * rounds,
+                                                             threads, unroll, &p.strips, &p.strip,
+                                                             &p.chunk_lines))
+                                            continue;
+                                        if (p.strip / vec > threads) continue;
+                                        out.push_back(p);
+                                    }
+                }
+            }
+    }
     std::vector<int> vecs;
+    if (vmax >= 8) vecs.push_back(8);
     if (vmax >= 4) vecs.push_back(4);
     if (vmax >= 2) vecs.push_back(2);
     if (effort > 0 || vmax == 1) vecs.push_back(1);
-    if (effort == 0 && vecs.size() > 1) vecs.resize(1 + (vmax >= 4 ? 1 : 0));
+    if (effort == 0 && vecs.size() > 2) vecs.resize(2);
     const std::vector<int> threads_l = effort ? std::vector<int>{256, 512, 1024}
                                               : std::vector<int>{512, 1024};
     const std::vector<int> unrolls = effort ? std::vector<int>{4, 8, 16} : std::vector<int>{4, 8};
@@ -236,7 +284,8 @@ std::vector<rc_plan> candidates(int64_t lines, int32_t detectors, int32_t bands,
                                        : std::vector<int>{1, 2, 4};
     // LDS paths: the two widest strips that fit (the measured throughput of
     // strip-shaped streams grows with the strip width).
-    for (int path : {RC_PATH_PACKED, RC_PATH_LDS}) {
+    for (int path : {RC_PATH_PACKED, RC_PATH_LDS, RC_PATH_DENSE}) {
+        if (path == RC_PATH_DENSE && levels > kDenseMaxLevels) continue;
         std::vector<int> widths;
         for (int W = 256; W >= 8 && widths.size() < 2; W >>= 1) {
             if (plan_lds_bytes(path, W, levels) > di.lds) continue;
@@ -248,7 +297,10 @@ std::vector<rc_plan> candidates(int64_t lines, int32_t detectors, int32_t bands,
                 for (int threads : threads_l)
                     for (int unroll : unrolls)
                         for (int nt = 0; nt < 3; ++nt)
-                            for (int k : ks) add(path, W, vec, threads, unroll, nt, k);
+                            for (int k : ks) {
+                                if (vec == 8 && unroll != 4) continue;
+                                add(path, W, vec, threads, unroll, nt, k);
+                            }
     }
     // The L2 path: a few shapes, line chunks sized so an XCD's CUs share a strip.
     for (int W : {32, 64, 128})
@@ -272,7 +324,7 @@ rc_status rc_tune(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_
     if (!dn || !lut || !out || dn == out) return RC_EINVAL;
     const DeviceInfo* di = current_device();
     if (!di) return RC_EHIP;
-    const int vmax = max_vec(dn, out, detectors);
+    const int vmax = max_vec(dn, out, detectors, 8);
     std::vector<rc_plan> cands = candidates(lines, detectors, bands, levels, vmax, *di, effort);
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);

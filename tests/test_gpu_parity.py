@@ -149,6 +149,74 @@ def test_correct_forced_plans(o, shape):
         assert np.array_equal(out.host(), want), f"plan {plan}"
 
 
+UNEVEN_SHAPES = [(3, 401, 6000, 4096), (2, 257, 1000, 1024), (1, 1000, 24, 1024), (2, 33, 8, 3),
+                 (1, 100, 1000, 65536)]
+
+
+@pytest.mark.parametrize("shape", UNEVEN_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_uneven_strips(o, shape):
+    """Strips of nearly equal, non-power-of-two widths (the `strips` plan
+    field), 1 to 8 pixels per lane (8: 16-byte accesses), every LUT mode,
+    line chunks that leave a ragged last chunk."""
+    B, N, D, L = shape
+    coeffs, dn = pins.tiny_case(D + L, B, N, D, L)
+    rng = np.random.default_rng(D)
+    coeffs[..., 0] = rng.normal(0, L / 128, size=(B, D))
+    coeffs[..., 1] = rng.uniform(0.9, 1.1, size=(B, D))
+    coeffs[..., 2] = rng.normal(0, 0.05 / L, size=(B, D))
+    coeffs[..., 3] = 0.0
+    want_lut, want = expect(o, coeffs, dn, L)
+    lut_t = rc.lut_build(to_dev_f64(coeffs), L)
+    dn_t = to_dev_u16(dn)
+    n = 0
+    for path, vec, strips, threads, unroll, chunk, nt, lmap in itertools.product(
+            (rc.RC_PATH_PACKED, rc.RC_PATH_LDS, rc.RC_PATH_L2, rc.RC_PATH_DENSE), (8, 4, 2, 1),
+            (1, 3, 7, 85),
+            (256, 1024), (4, 8), (N, 37), (0, 2, 4, 5), (0, 1)):
+        if D % vec or strips > D // vec:
+            continue
+        if (vec + strips + threads + unroll + chunk + nt + 5 * lmap) % 7:  # thin the grid
+            continue
+        widest = vec * -(-(D // vec) // strips)
+        W = 1
+        while W < widest:
+            W <<= 1
+        lds = {rc.RC_PATH_LDS: W * L * 2, rc.RC_PATH_PACKED: (L + 31) // 32 * W * 10,
+               rc.RC_PATH_DENSE: (L + 63) // 64 * W * 10, rc.RC_PATH_L2: 0}[path]
+        if lds > 160 * 1024 or W > 1024 or W // vec > threads:
+            continue
+        if path == rc.RC_PATH_DENSE and L > 8192:
+            continue
+        if vec == 8 and unroll != 4:
+            continue
+        plan = rc.Plan(path=path, strip=W, vec=vec, threads=threads, unroll=unroll,
+                       chunk_lines=chunk, xcd_remap=1, nontemporal=nt, strips=strips,
+                       lane_map=lmap)
+        out = Guarded((B, N, D))
+        rc.correct(dn_t, lut_t, out=out.t, plan=plan)
+        torch.cuda.synchronize()
+        out.check_pads()
+        assert np.array_equal(out.host(), want), f"plan {plan}"
+        n += 1
+    assert n >= 3
+
+
+def test_uneven_plan_rejects():
+    """strips beyond the unit count, or strips wider than W: RC_EINVAL."""
+    dn = torch.zeros((1, 4, 64), dtype=torch.int16, device=dev())
+    lut = torch.zeros((1, 64, 1024), dtype=torch.int16, device=dev())
+    base = dict(path=rc.RC_PATH_PACKED, strip=64, vec=8, threads=256, unroll=4, chunk_lines=4,
+                xcd_remap=1, nontemporal=0, strips=1)
+    for upd in ({"strips": 9}, {"strips": 1, "strip": 32}, {"strips": -1}, {"unroll": 8}):
+        d = dict(base)
+        d.update(upd)
+        with pytest.raises(rc.RcError) as e:
+            rc.correct(dn, lut, plan=rc.Plan(**d))
+        assert e.value.status == rc.RC_EINVAL, upd
+    rc.correct(dn, lut, plan=rc.Plan(**base))
+    torch.cuda.synchronize()
+
+
 PACKED_SHAPES = [(2, 301, 1000, 1024), (1, 77, 333, 1000), (3, 40, 50, 3), (1, 65, 130, 4096),
                  (1, 9, 64, 33), (2, 31, 520, 2048)]
 
@@ -185,6 +253,67 @@ def test_packed_path(o, shape, packable):
         torch.cuda.synchronize()
         out.check_pads()
         assert np.array_equal(out.host(), want), f"plan {plan}"
+
+
+DENSE_SHAPES = [(2, 301, 1000, 4096), (1, 77, 333, 1000), (3, 40, 64, 64), (1, 65, 130, 8192),
+                (2, 31, 520, 2048), (1, 50, 40, 100), (2, 20, 24, 2)]
+
+
+@pytest.mark.parametrize("shape", DENSE_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("rows", ["calibration", "clamped", "unpackable"])
+def test_dense_path(o, shape, rows):
+    """Dense LDS tiles (1 bit per step, per-block slope, saturated runs
+    extrapolated): exact for calibration-like rows, for rows that saturate
+    at both ends inside a block, and through the global-gather fallback for
+    rows that do not fit (decreasing, steep, or steps of 0 and 2 in a block)."""
+    B, N, D, L = shape
+    coeffs, dn = pins.tiny_case(L + N + D, B, N, D, L)
+    rng = np.random.default_rng(L + D + N)
+    coeffs[..., 0] = rng.normal(0, L / 128, size=(B, D))
+    coeffs[..., 1] = rng.uniform(0.9, 1.1, size=(B, D))
+    coeffs[..., 2] = rng.normal(0, 0.05 / L, size=(B, D))
+    coeffs[..., 3] = 0.0
+    if rows == "clamped":
+        # Offsets of +-L/4 and gains up to 1.6: long runs of 0 and L-1, the
+        # transitions anywhere inside a 64-level block.
+        coeffs[..., 0] = rng.uniform(-L / 4, L / 4, size=(B, D))
+        coeffs[..., 1] = rng.uniform(0.6, 1.6, size=(B, D))
+    if rows == "unpackable":
+        coeffs[0, D // 2] = [L - 1, -1.0, 0, 0]      # decreasing
+        coeffs[-1, 0] = [0, 5.0, 0, 0]               # steps of 5
+        coeffs[-1, D - 1] = [L / 3, 1.0, 3.0 / L, 0]  # slope growing from 1 to 7
+    want_lut, want = expect(o, coeffs, dn, L)
+    lut_t = rc.lut_build(to_dev_f64(coeffs), L)
+    dn_t = to_dev_u16(dn)
+    n = 0
+    for strip, vec, threads, unroll, chunk, nt, strips in (
+            (256, 8, 256, 4, N, 0, 0), (64, 2, 512, 8, 7, 2, 0), (16, 1, 1024, 16, 3, 4, 0),
+            (128, 4, 256, 4, 1, 0, 0), (256, 4, 256, 8, N, 0, 3), (128, 2, 1024, 8, 11, 5, 2),
+            (256, 1, 256, 8, N, 0, 0)):
+        if D % vec or -(-L // 64) * strip * 10 > 160 * 1024 or strip // vec > threads:
+            continue
+        if strips and (strips > D // vec or vec * -(-(D // vec) // strips) > strip):
+            continue
+        plan = rc.Plan(path=rc.RC_PATH_DENSE, strip=strip, vec=vec, threads=threads,
+                       unroll=unroll, chunk_lines=chunk, xcd_remap=1, nontemporal=nt,
+                       strips=strips)
+        out = Guarded((B, N, D))
+        rc.correct(dn_t, lut_t, out=out.t, plan=plan)
+        torch.cuda.synchronize()
+        out.check_pads()
+        assert np.array_equal(out.host(), want), f"plan {plan}"
+        n += 1
+    assert n >= 2
+
+
+def test_dense_rejects_long_rows():
+    dn = torch.zeros((1, 4, 64), dtype=torch.int16, device=dev())
+    lut = torch.zeros((1, 64, 8200), dtype=torch.int16, device=dev())
+    plan = rc.Plan(path=rc.RC_PATH_DENSE, strip=16, vec=2, threads=256, unroll=4, chunk_lines=4,
+                   xcd_remap=1, nontemporal=0)
+    with pytest.raises(rc.RcError) as e:
+        rc.correct(dn, lut, plan=plan)
+    assert e.value.status == rc.RC_EINVAL
 
 
 def test_tuner_roundtrip(tmp_path):
@@ -224,7 +353,8 @@ def test_plan_rejected_when_lds_too_small():
     assert e.value.status == rc.RC_EINVAL
 
 
-@pytest.mark.parametrize("field,value", [("nontemporal", 3), ("nontemporal", -1), ("xcd_remap", 2)])
+@pytest.mark.parametrize("field,value", [("nontemporal", 6), ("nontemporal", -1), ("xcd_remap", 2),
+                                         ("lane_map", 2), ("lane_map", -1)])
 def test_plan_rejects_bad_policy(field, value):
     dn = torch.zeros((1, 4, 64), dtype=torch.int16, device=dev())
     lut = torch.zeros((1, 64, 1024), dtype=torch.int16, device=dev())
