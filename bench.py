@@ -1,10 +1,13 @@
 """Benchmark: LUT build + image correction on one MI355X.
 
-One step = rc_lut_build + rc_correct over the 4-band x 12000-line x 12000-detector
-scene (L = 1024, quadratic coefficients), inputs resident in HBM. Prints one
-JSON line with whole-step Gpix/s, the correction kernel's roofline position
-(algorithmic bytes / HIP-event duration vs 8 TB/s), the CPU oracle's rate on
-this host, and whether the GPU output is bit-identical to the oracle's.
+One step = rc_lut_build + rc_correct over the 3-band x 50000-line x 6000-detector
+scene (L = 4096, cubic coefficients; the largest single-scene workload), inputs
+resident in HBM. Prints one JSON line with whole-step Gpix/s, the correction
+kernel's roofline position (algorithmic bytes / HIP-event duration vs 8 TB/s),
+the CPU oracle's rate on this host, and whether the GPU output is
+bit-identical to the oracle's; beside it the 4 x 12000 x 12000 scene with its
+own roofline, end-to-end (pinned host to pinned host) throughput, and the
+batch, serving, fit and demosaicing legs.
 """
 import argparse
 import hashlib
@@ -29,7 +32,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--workload", type=int, default=2, choices=(0, 1, 2))
+    ap.add_argument("--no-scenes", action="store_true",
+                    help="skip the other single-scene workload (1 or 2)")
+    ap.add_argument("--no-e2e", action="store_true",
+                    help="skip the end-to-end (pinned host to host) leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -40,7 +47,7 @@ def parse():
     ap.add_argument("--no-demosaic", action="store_true", help="skip the demosaicing legs")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the graph-replayed 1 x 1024 x 1024 scene")
-    ap.add_argument("--serve-jobs", type=int, default=300)
+    ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--serve-qps", type=float, default=150.0)
     ap.add_argument("--batch-requests", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -320,6 +327,123 @@ def bench_demosaic(args, torch, rc, dev, method="bilinear"):
     return res
 
 
+def bench_e2e(args, torch, rc, dev, s):
+    """End to end: the scene starts in pinned host memory and its correction
+    must end there. (a) Plain path, pipelined in line chunks: H2D of a chunk
+    on one copy stream, rc_correct of that chunk on the compute stream (after
+    rc_lut_build from the copied coefficients), D2H on a second copy stream,
+    each step waiting on the previous one's event; timed on the host from the
+    first copy to the last copy's completion. (b) The same scene as one job
+    of rc_server. Compared with the pinned-copy ceiling: the image copied
+    H2D and D2H at once on two streams (no kernels)."""
+    import oracle
+    coeffs = s.coeffs()
+    dn = s.dn()
+    px = s.pixels
+    B, N, D, L = s.bands, s.lines, s.detectors, s.levels
+    h_dn = rc.pinned_empty((B, N, D), np.uint16)
+    h_dn[...] = dn
+    h_out = rc.pinned_empty((B, N, D), np.uint16)
+    h_c = rc.pinned_empty((B, D, 4), np.float64)
+    h_c[...] = coeffs
+    d_dn = torch.empty((B, N, D), dtype=torch.int16, device=dev)
+    d_out = torch.empty_like(d_dn)
+    d_lut = torch.empty((B, D, L), dtype=torch.int16, device=dev)
+    d_c = torch.empty((B, D, 4), dtype=torch.float64, device=dev)
+    s_in, s_comp, s_out = (torch.cuda.Stream(device=dev) for _ in range(3))
+    t_dn = torch.from_numpy(h_dn.view(np.int16))
+    t_out = torch.from_numpy(h_out.view(np.int16))
+    t_c = torch.from_numpy(h_c)
+    chunk = max(1, (32 << 20) // D)  # lines per chunk: about 32 Mi pixels
+
+    def pipeline():
+        pieces = []
+        with torch.cuda.stream(s_in):
+            d_c.copy_(t_c, non_blocking=True)
+            ev_c = torch.cuda.Event()
+            ev_c.record(s_in)
+        s_comp.wait_event(ev_c)
+        rc.rc_lut_build(d_c, B, D, L, d_lut, s_comp)
+        for b in range(B):
+            for n0 in range(0, N, chunk):
+                n1 = min(N, n0 + chunk)
+                e_in, e_k = torch.cuda.Event(), torch.cuda.Event()
+                with torch.cuda.stream(s_in):
+                    d_dn[b, n0:n1].copy_(t_dn[b, n0:n1], non_blocking=True)
+                    e_in.record(s_in)
+                s_comp.wait_event(e_in)
+                rc.rc_correct(d_dn[b, n0:n1], d_lut[b], n1 - n0, D, 1, L, d_out[b, n0:n1],
+                              s_comp)
+                e_k.record(s_comp)
+                s_out.wait_event(e_k)
+                with torch.cuda.stream(s_out):
+                    t_out[b, n0:n1].copy_(d_out[b, n0:n1], non_blocking=True)
+                pieces.append(n1 - n0)
+        return len(pieces)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    chunks = pipeline()
+    torch.cuda.synchronize()
+    plain_s = timed(pipeline)
+    o = oracle.get()
+    want = o.correct(dn, o.lut_build(coeffs, L))
+    plain_exact = bool(np.array_equal(h_out, want))
+
+    def copies_only():
+        with torch.cuda.stream(s_in):
+            d_dn.copy_(t_dn, non_blocking=True)
+        with torch.cuda.stream(s_out):
+            t_out.copy_(d_out, non_blocking=True)
+
+    copy_s = timed(copies_only)
+    del d_dn, d_out, d_lut, d_c
+    torch.cuda.empty_cache()
+
+    # The same scene as one rc_server job (its own pieces, arena, streams).
+    h_out[...] = 0
+    srv = rc.Server()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        jid = srv.submit(h_c, h_dn, h_out, L)
+        st = srv.wait(jid)
+        times.append(time.perf_counter() - t0)
+        if st["status"] != rc.RC_OK:
+            break
+    srv.close()
+    server_s = statistics.median(times)
+    server_exact = bool(np.array_equal(h_out, want))
+    host_bytes = 4 * px + B * D * 32
+
+    def rates(sec):
+        return {"s": round(sec, 4), "gpix_s": round(px / sec / 1e9, 2),
+                "gb_s": round(host_bytes / sec / 1e9, 1),
+                "frac_copy_ceiling": round(copy_s / sec, 3),
+                "frac_hbm": round((4 * px + 2 * B * D * L * 2) / sec / 1e9 / HBM_PEAK_GBS, 5)}
+
+    return {"workload": s.name, "host_bytes": host_bytes,
+            "pinned_copy_ceiling": {"s": round(copy_s, 4),
+                                    "gb_s": round(4 * px / copy_s / 1e9, 1),
+                                    "gpix_s": round(px / copy_s / 1e9, 2),
+                                    "note": "image H2D and D2H at once on two streams"},
+            "plain_pipelined": dict(rates(plain_s), chunks=chunks, lines_per_chunk=chunk,
+                                    bit_exact=plain_exact),
+            "server_one_job": dict(rates(server_s), bit_exact=server_exact),
+            "note": "pinned host DN + coefficients in, pinned host out; frac_copy_ceiling = "
+                    "copy-only time / end-to-end time; frac_hbm counts image I/O and the LUT "
+                    "written and read once on the device"}
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -342,17 +466,23 @@ def bench_serve(args, torch, rc, dev):
     trace = gen.serve_trace(args.serve_jobs, qps=args.serve_qps)
     max_px = max(j.pixels for _, j in trace)
     t0 = time.time()
-    # Host data: per bit depth one pinned pool of seeded DN holding the largest
-    # job; a job's image is the pool's first pixels in its own shape. Outputs
-    # of unverified jobs share one pinned sink per depth.
+    # Host data: per bit depth one pinned pool of seeded DN, several times the
+    # largest job; job i's image is the pool slice at an offset drawn from a
+    # generator seeded with i (distinct data per job without holding every
+    # job's image: 2000 jobs average 94 Mpix). Outputs of unverified jobs
+    # share one pinned sink per depth.
+    pool_px = max(4 * max_px, 1 << 30)
     pools, sinks = {}, {}
     for depth, kind in ((10, gen.DN_GAUSS_SAT10), (12, gen.DN_SCENE12)):
-        pool = rc.pinned_empty((max_px,), np.uint16)
-        rows = max_px // 4096 + 1
+        pool = rc.pinned_empty((pool_px,), np.uint16)
+        rows = pool_px // 4096 + 1
         tmp = gen.dn(gen.BASE_SEED + 4, 4, 1000 + depth, kind, 1, rows, 4096)
-        pool[:] = tmp.reshape(-1)[:max_px]
+        pool[:] = tmp.reshape(-1)[:pool_px]
+        del tmp
         pools[depth] = pool
         sinks[depth] = rc.pinned_empty((max_px,), np.uint16)
+    offsets = [int(np.random.default_rng(gen.BASE_SEED + 4 + i).integers(0, pool_px - j.pixels + 1))
+               for i, (_, j) in enumerate(trace)]
     depth_of = lambda j: 10 if j.levels == 1024 else 12
     coeffs = []
     for _, j in trace:
@@ -367,7 +497,8 @@ def bench_serve(args, torch, rc, dev):
 
     def dn_of(i):
         j = trace[i][1]
-        return pools[depth_of(j)][:j.pixels].reshape(j.bands, j.lines, j.detectors)
+        o = offsets[i]
+        return pools[depth_of(j)][o:o + j.pixels].reshape(j.bands, j.lines, j.detectors)
 
     def out_of(i):
         j = trace[i][1]
@@ -415,6 +546,7 @@ def bench_serve(args, torch, rc, dev):
     stats, info = run_server()
     ok = all(st["status"] == rc.RC_OK for st in stats)
     lat = [st["latency_s"] for st in stats]
+    waits = [st["admit_s"] - st["submit_s"] for st in stats]
     first = min(st["submit_s"] for st in stats)
     last = max(st["done_s"] for st in stats)
     px = sum(j.pixels for _, j in trace)
@@ -450,11 +582,17 @@ def bench_serve(args, torch, rc, dev):
     plain_span = plain_done[-1] - trace[0][0]
     return {
         "workload": f"{len(trace)} jobs, Poisson arrivals at {args.serve_qps:g} jobs/s, "
-                    "log-uniform 1-600 Mpix, 1-4 bands, 10/12-bit, pinned host buffers",
+                    "log-uniform 1-600 Mpix, 1-4 bands, 10/12-bit, pinned host buffers, "
+                    "each job's image at its own seeded offset of a "
+                    f"{pool_px / 2**30:.1f} Gi-pixel pool per bit depth",
+        "jobs": len(trace),
         "pixels": px, "offered_gpix_s": round(px / trace[-1][0] / 1e9, 2),
         "served_gpix_s": round(px / (last - first) / 1e9, 2),
         "p50_latency_ms": round(percentile(lat, 50) * 1e3, 2),
         "p99_latency_ms": round(percentile(lat, 99) * 1e3, 2),
+        "p50_admission_wait_ms": round(percentile(waits, 50) * 1e3, 3),
+        "p99_admission_wait_ms": round(percentile(waits, 99) * 1e3, 3),
+        "max_admission_wait_ms": round(max(waits) * 1e3, 3),
         "plain_gpix_s": round(px / plain_span / 1e9, 2),
         "plain_p50_latency_ms": round(percentile(plain_lat, 50) * 1e3, 2),
         "plain_p99_latency_ms": round(percentile(plain_lat, 99) * 1e3, 2),
@@ -505,63 +643,70 @@ def cpu_model():
     return platform.processor()
 
 
-def main():
-    args = parse()
-    if args.calibrate_copy:
-        calibrate_copy(args.calibrate_copy)
-        return
-    if args.gpus != 1:
-        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the work shards "
-              "by band and detector strip with no exchange between GPUs, so it is not run here.",
-              file=sys.stderr)
-        sys.exit(2)
+def copy_plan_default(rc):
+    """Launch shape of the linear-copy ceiling: one 256-thread workgroup per
+    CU, 4 x 16 bytes in flight per lane, non-temporal loads and stores (the
+    fastest shape of a sweep over 256-1024 threads, 2-8 loads, 1-8
+    workgroups per CU and three cache policies on 1.15 and 1.8 GB copies)."""
+    return rc.CopyPlan(threads=256, unroll=4, policy=1, wgs_per_cu=1)
 
-    import torch
 
-    import gen
-    import paper_1505_05655_amd as rc
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    s = gen.workload(args.workload)
+def measure_scene(args, torch, rc, dev, s, steps, warmup, cpu_seconds, verify, cpu_baseline):
+    """One single-scene workload: K timed steps of rc_lut_build + rc_correct
+    (HIP events around each kernel on the launch stream, plus the wall clock
+    of the whole loop), cold-cache steps, the copy ceilings of the same image,
+    the CPU oracle timed on this host, and a bit-exact check."""
+    import oracle
     t0 = time.time()
     coeffs = s.coeffs()
     dn = s.dn()
-    gen_s = time.time() - t0
-    print(f"[bench] workload {s.name}: {s.pixels / 1e6:.1f} Mpix generated in {gen_s:.1f}s",
-          file=sys.stderr, flush=True)
-
+    print(f"[bench] workload {s.name}: {s.pixels / 1e6:.1f} Mpix generated in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     c_t = torch.from_numpy(coeffs).to(dev)
     dn_t = torch.from_numpy(dn.view(np.int16)).to(dev)
     lut_t = torch.empty((s.bands, s.detectors, s.levels), dtype=torch.int16, device=dev)
     out_t = torch.empty_like(dn_t)
     stream = torch.cuda.Stream(device=dev)  # default priority
     plan, tuned = rc.rc_plan_for(s.lines, s.detectors, s.bands, s.levels, dn_t, out_t)
+    # Long LUT rows: the correction with a workspace (the LUT encoded once for
+    # the whole scene, then the dense tiles), else the plain call.
+    ws_bytes = rc.rc_correct_ws_bytes(s.detectors, s.bands, s.levels)
+    ws_t = torch.empty(max(ws_bytes, 256) // 2, dtype=torch.int16, device=dev)
+
+    def correct_plain():
+        rc.rc_correct(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, stream)
+
+    def correct_ws():
+        rc.rc_correct_ws(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, ws_t,
+                         ws_bytes, None, stream)
+
+    correct = correct_ws if ws_bytes else correct_plain
+    entry = "rc_correct_ws" if ws_bytes else "rc_correct"
 
     def step():
         rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
-        rc.rc_correct(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, stream)
+        correct()
 
     torch.cuda.synchronize()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
 
     # Timed region: K whole steps, events around each kernel on the launch stream.
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         ev[k][0].record(stream)
         rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
         ev[k][1].record(stream)
-        rc.rc_correct(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, stream)
+        correct()
         ev[k][2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    build_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps)]
-    apply_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps)]
-    ms_per_step = wall * 1e3 / args.steps
+    build_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+    apply_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
+    ms_per_step = wall * 1e3 / steps
 
     px = s.pixels
     lut_bytes = s.bands * s.detectors * s.levels * 2
@@ -569,11 +714,9 @@ def main():
     build_bytes = lut_bytes + s.bands * s.detectors * 32  # LUT written + coefficients read
     apply_avg = statistics.mean(apply_ms)
     achieved = apply_bytes / (apply_avg * 1e-3) / 1e9
-    value = px / (ms_per_step * 1e-3) / 1e9
 
-    # Cold caches, reported beside the headline (not part of it): before each
-    # of 10 extra steps a 512 MiB scratch write evicts the LUT from L2 and the
-    # 256 MB MALL; events around each kernel as above.
+    # Cold caches: before each of 10 extra steps a 512 MiB scratch write
+    # evicts the LUT from L2 and the 256 MB MALL; events around each kernel.
     scratch = torch.empty(256 << 20, dtype=torch.int16, device=dev)
     cold_b, cold_a = [], []
     for _ in range(10):
@@ -583,38 +726,54 @@ def main():
         e[0].record(stream)
         rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
         e[1].record(stream)
-        rc.rc_correct(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, stream)
+        correct()
         e[2].record(stream)
         stream.synchronize()
         cold_b.append(e[0].elapsed_time(e[1]))
         cold_a.append(e[1].elapsed_time(e[2]))
     del scratch
+    cold_avg = statistics.mean(cold_a)
 
-    # Practical ceiling beside the roofline: a plain device-to-device copy of
-    # the same image (2 B read + 2 B written per pixel, no LUT) on the same
-    # stream, timed the same way.
+    # Practical ceilings beside the roofline: plain copies of the same image
+    # (2 B read + 2 B written per pixel, no LUT) on the same stream, timed the
+    # same way: the library's hand-written linear copy and torch's.
     cp_t = torch.empty_like(dn_t)
-    cp_ms = []
-    for i in range(23):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        e[0].record(stream)
+    cplan = copy_plan_default(rc)
+
+    def time_copy(fn, n=20):
+        res = []
+        for i in range(n + 3):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record(stream)
+            fn()
+            e[1].record(stream)
+            if i >= 3:
+                res.append(e)
+        stream.synchronize()
+        return [a.elapsed_time(b) for a, b in res]
+
+    # The plain call on the same scene (when the headline uses the workspace);
+    # the headline path's output is kept for the bit-exact check first.
+    head_out = out_t.cpu().numpy().view(np.uint16) if ws_bytes else None
+    plain_ms = time_copy(correct_plain, 10) if ws_bytes else None
+    rc_cp_ms = time_copy(lambda: rc.rc_stream_copy(dn_t, cp_t, 2 * px, cplan, stream))
+    copy_ok = bool(torch.equal(cp_t, dn_t))
+
+    def torch_copy():
         with torch.cuda.stream(stream):
             cp_t.copy_(dn_t)
-        e[1].record(stream)
-        if i >= 3:
-            cp_ms.append(e)
-    stream.synchronize()
-    cp_ms = [a.elapsed_time(b) for a, b in cp_ms]
+
+    th_cp_ms = time_copy(torch_copy)
     del cp_t
-    copy_gbs = 4 * px / (statistics.mean(cp_ms) * 1e-3) / 1e9
+    rc_copy_gbs = 4 * px / (statistics.mean(rc_cp_ms) * 1e-3) / 1e9
+    th_copy_gbs = 4 * px / (statistics.mean(th_cp_ms) * 1e-3) / 1e9
 
     bit_exact = None
     cpu = None
-    if not args.no_cpu_baseline or not args.no_verify:
-        import oracle
+    if cpu_baseline or verify:
         o = oracle.get()
         # The oracle is single-threaded; time whole passes of the same step
-        # (LUT build + correction) until at least --cpu-seconds have elapsed.
+        # (LUT build + correction) until at least cpu_seconds have elapsed.
         # The calling thread is pinned to one core while it runs the oracle.
         want = np.empty_like(dn)
         affinity = os.sched_getaffinity(0)
@@ -633,14 +792,14 @@ def main():
                 o.correct(dn, want_lut, out=want)
                 passes += 1
                 el = time.perf_counter() - c0
-                if args.no_cpu_baseline or el >= args.cpu_seconds:
+                if not cpu_baseline or el >= cpu_seconds:
                     break
         finally:
             try:
                 os.sched_setaffinity(0, affinity)
             except OSError:
                 pass
-        if not args.no_cpu_baseline:
+        if cpu_baseline:
             cpu = {"value": round(px * passes / el / 1e9, 4), "unit": "Gpix/s", "cores": 1,
                    "kind": "oracle",
                    "lut_build_s": round(build_s / passes, 4),
@@ -648,23 +807,116 @@ def main():
                    "sample": f"{passes} full pass(es) of the same step (LUT build + correction "
                              f"of all {px} pixels), {el:.1f}s, single-threaded, {pinned}, host "
                              f"{cpu_model()} with {os.cpu_count()} logical CPUs"}
-        if not args.no_verify:
+        if verify:
             got = out_t.cpu().numpy().view(np.uint16)
             got_lut = lut_t.cpu().numpy().view(np.uint16)
             bit_exact = bool(np.array_equal(got, want) and np.array_equal(got_lut, want_lut))
+            if head_out is not None:  # both the workspace path and the plain call
+                bit_exact = bit_exact and bool(np.array_equal(head_out, want))
+    del dn_t, out_t, lut_t, c_t, ws_t
+    torch.cuda.empty_cache()
 
+    return {
+        "workload": s.name, "config": {"workload": s.name, "bands": s.bands, "lines": s.lines,
+                                       "detectors": s.detectors, "levels": s.levels,
+                                       "seed": s.seed, "entry_point": entry,
+                                       "workspace_bytes": ws_bytes,
+                                       "plan": None if ws_bytes else plan.as_dict(),
+                                       "plan_tuned": None if ws_bytes else tuned},
+        "value": round(px / (ms_per_step * 1e-3) / 1e9, 3),
+        "ms_per_step": round(ms_per_step, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(s.name),
+                     "kernel": ("correction: k_dense_encode + k_apply (rc_correct_ws)"
+                                if ws_bytes else "lut_apply (k_apply)"),
+                     "algorithmic_bytes": apply_bytes,
+                     "launch_ms_mean": round(apply_avg, 4),
+                     "frac_cold": round(apply_bytes / (cold_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "cpu_baseline": cpu,
+        "bit_exact": bit_exact,
+        "kernels": {
+            "lut_apply_ms": {"mean": round(apply_avg, 4), "min": round(min(apply_ms), 4),
+                             "median": round(statistics.median(apply_ms), 4),
+                             "p10": round(percentile(apply_ms, 10), 4),
+                             "p90": round(percentile(apply_ms, 90), 4)},
+            "lut_apply_gpix_s": round(px / (apply_avg * 1e-3) / 1e9, 2),
+            "plain_rc_correct": None if not ws_bytes else {
+                "ms_mean": round(statistics.mean(plain_ms), 4),
+                "frac_hbm": round(apply_bytes / (statistics.mean(plain_ms) * 1e-3) / 1e9 /
+                                  HBM_PEAK_GBS, 4),
+                "plan": plan.as_dict(), "plan_tuned": tuned},
+            "lut_build_ms": {"mean": round(statistics.mean(build_ms), 4),
+                             "min": round(min(build_ms), 4),
+                             "median": round(statistics.median(build_ms), 4),
+                             "p10": round(percentile(build_ms, 10), 4),
+                             "p90": round(percentile(build_ms, 90), 4)},
+            "lut_build_gb_s": round(build_bytes / (statistics.mean(build_ms) * 1e-3) / 1e9, 1),
+            "cold_caches": {"lut_apply_ms_mean": round(cold_avg, 4),
+                            "lut_apply_ms_median": round(statistics.median(cold_a), 4),
+                            "lut_build_ms_median": round(statistics.median(cold_b), 4),
+                            "frac_hbm": round(apply_bytes / (cold_avg * 1e-3) / 1e9 /
+                                              HBM_PEAK_GBS, 4),
+                            "steps": len(cold_a),
+                            "note": "512 MiB scratch write before each step"},
+            "copy_ceiling": {
+                "rc_stream_copy_ms_mean": round(statistics.mean(rc_cp_ms), 4),
+                "rc_stream_copy_gb_s": round(rc_copy_gbs, 1),
+                "rc_stream_copy_frac": round(rc_copy_gbs / HBM_PEAK_GBS, 4),
+                "rc_stream_copy_plan": cplan.as_dict(), "rc_stream_copy_exact": copy_ok,
+                "torch_copy_ms_mean": round(statistics.mean(th_cp_ms), 4),
+                "torch_copy_gb_s": round(th_copy_gbs, 1),
+                "lut_apply_vs_rc_copy": round(achieved / rc_copy_gbs, 3),
+                "note": "device-to-device copies of the input image (4 B per pixel moved), "
+                        "20 launches each on the launch stream"},
+        },
+    }
+
+
+def main():
+    args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+    if args.gpus != 1:
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the work shards "
+              "by band and detector strip with no exchange between GPUs, so it is not run here.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_1505_05655_amd as rc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    head = measure_scene(args, torch, rc, dev, gen.workload(args.workload), args.steps,
+                         args.warmup, args.cpu_seconds, not args.no_verify,
+                         not args.no_cpu_baseline)
+    # The other single-scene workloads, each with its own roofline (10 timed
+    # steps, bit-exact check, no CPU timing).
+    scenes = []
+    if not args.no_scenes:
+        for w in (1, 2):
+            if w == args.workload:
+                continue
+            r = measure_scene(args, torch, rc, dev, gen.workload(w), 10, 3, 0.0,
+                              not args.no_verify, False)
+            r.pop("cpu_baseline")
+            scenes.append(r)
+
+    e2e_res = None if args.no_e2e else [bench_e2e(args, torch, rc, dev, gen.workload(w))
+                                        for w in (args.workload,)]
     fit_res = None if args.no_fit else bench_fit(args, torch, rc, dev)
     demosaic_res = None if args.no_demosaic else bench_demosaic(args, torch, rc, dev)
     gradient_res = (None if args.no_demosaic else
                     bench_demosaic(args, torch, rc, dev, method="gradient"))
-
     small_res = None if args.no_small else bench_small(args, torch, rc, dev)
 
     batch_res = None
-    del dn_t, out_t, lut_t, c_t
     torch.cuda.empty_cache()
     if not args.no_batch:
-        torch.cuda.empty_cache()
         print("[bench] batch leg", file=sys.stderr, flush=True)
         batch_res = bench_batch(args, torch, rc, dev)
 
@@ -676,49 +928,24 @@ def main():
     props = torch.cuda.get_device_properties(dev)
     line = {
         "metric": "corrected Gpix/s (LUT build + correction per step), bit-exact vs CPU oracle",
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "Gpix/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u16 gather (LUT build in f64)",
         "data": "synthetic, seeded",
-        "config": {"workload": s.name, "bands": s.bands, "lines": s.lines,
-                   "detectors": s.detectors, "levels": s.levels, "seed": s.seed,
-                   "plan": plan.as_dict(), "plan_tuned": tuned},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(s.name),
-                     "kernel": "lut_apply", "algorithmic_bytes": apply_bytes},
-        "cpu_baseline": cpu,
-        "bit_exact": bit_exact,
-        "kernels": {
-            "lut_apply_ms": {"mean": round(apply_avg, 4), "min": round(min(apply_ms), 4),
-                             "median": round(statistics.median(apply_ms), 4),
-                             "p10": round(percentile(apply_ms, 10), 4),
-                             "p90": round(percentile(apply_ms, 90), 4)},
-            "lut_apply_gpix_s": round(px / (apply_avg * 1e-3) / 1e9, 2),
-            "lut_build_ms": {"mean": round(statistics.mean(build_ms), 4),
-                             "min": round(min(build_ms), 4),
-                             "median": round(statistics.median(build_ms), 4),
-                             "p10": round(percentile(build_ms, 10), 4),
-                             "p90": round(percentile(build_ms, 90), 4)},
-            "lut_build_gb_s": round(build_bytes / (statistics.mean(build_ms) * 1e-3) / 1e9, 1),
-            "cold_caches": {"lut_apply_ms_median": round(statistics.median(cold_a), 4),
-                            "lut_build_ms_median": round(statistics.median(cold_b), 4),
-                            "steps": len(cold_a),
-                            "note": "512 MiB scratch write before each step"},
-            "device_copy_same_image": {
-                "ms_mean": round(statistics.mean(cp_ms), 4),
-                "ms_median": round(statistics.median(cp_ms), 4),
-                "gb_s": round(copy_gbs, 1), "frac": round(copy_gbs / HBM_PEAK_GBS, 4),
-                "lut_apply_vs_copy": round(achieved / copy_gbs, 3),
-                "note": "torch device-to-device copy of the input image, 20 launches"},
-        },
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "cpu_baseline": head["cpu_baseline"],
+        "bit_exact": head["bit_exact"],
+        "kernels": head["kernels"],
+        "scenes": scenes,
+        "e2e": e2e_res,
         "fit": fit_res,
         "demosaic": demosaic_res,
         "demosaic_gradient": gradient_res,

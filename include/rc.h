@@ -177,6 +177,37 @@ typedef struct {
 rc_status rc_stream_copy(const void* src, void* dst, size_t bytes, const rc_copy_plan* plan,
                          hipStream_t stream);
 
+/* ---- correction with a workspace ------------------------------------------------------ */
+
+/*
+ * Workspace bytes rc_correct_ws needs for this shape: bands * ceil(levels /
+ * 64) * detectors * 10 bytes (rounded up to 256-byte pieces) when 2048 <=
+ * levels <= 8192, else 0 (no workspace used). Host only.
+ */
+size_t rc_correct_ws_bytes(int32_t detectors, int32_t bands, int32_t levels);
+
+/*
+ * The correction of rc_correct (same definition, same result bit for bit),
+ * for long LUT rows (2048 <= levels <= 8192) in two kernels: the first
+ * encodes every 64-level block of every LUT row into the dense form of
+ * RC_PATH_DENSE in the workspace (once for the whole LUT, on every CU), the
+ * second corrects with tiles that copy their strip's encoded blocks into LDS
+ * instead of encoding them (a strip split into line chunks is encoded once,
+ * not once per chunk). Other level counts: exactly rc_correct, ws ignored.
+ *   ws, ws_bytes  device workspace, 256-byte aligned, ws_bytes >=
+ *                 rc_correct_ws_bytes(...); caller-owned, contents
+ *                 overwritten, must not overlap dn, out or lut.
+ *   plan          NULL: the library's plan; else a RC_PATH_DENSE plan
+ *                 (validated as for rc_correct_plan).
+ * Allocates nothing, never synchronises (capturable). Two calls that share
+ * a workspace must be ordered (one stream): a later call overwrites it.
+ * Errors: as rc_correct; RC_EINVAL also for a missing, misaligned, short or
+ * overlapping workspace, or a plan that is not RC_PATH_DENSE.
+ */
+rc_status rc_correct_ws(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                        int32_t bands, int32_t levels, uint16_t* out, void* ws, size_t ws_bytes,
+                        const rc_plan* plan, hipStream_t stream);
+
 /* ---- least-squares calibration fit ---------------------------------------------------- */
 
 /*

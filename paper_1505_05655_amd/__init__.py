@@ -179,6 +179,11 @@ _lib.rc_server_info.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 _lib.rc_server_info.restype = ctypes.c_int
 _lib.rc_server_destroy.argtypes = [_vp]
 _lib.rc_server_destroy.restype = None
+_lib.rc_correct_ws_bytes.argtypes = [_i32, _i32, _i32]
+_lib.rc_correct_ws_bytes.restype = ctypes.c_size_t
+_lib.rc_correct_ws.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t,
+                               ctypes.POINTER(Plan), _vp]
+_lib.rc_correct_ws.restype = ctypes.c_int
 _lib.rc_stream_copy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(CopyPlan), _vp]
 _lib.rc_stream_copy.restype = ctypes.c_int
 _lib.rc_host_alloc.argtypes = [ctypes.c_size_t]
@@ -244,6 +249,18 @@ def rc_demosaic_gradient(raw, images, height, width, rgb, stream=None):
 def rc_correct(dn, lut, lines, detectors, bands, levels, out, stream=None):
     _check(_lib.rc_correct(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out),
                            _stream(stream)), "rc_correct")
+
+
+def rc_correct_ws_bytes(detectors, bands, levels):
+    """Workspace bytes rc_correct_ws needs (0: it uses none for this shape)."""
+    return int(_lib.rc_correct_ws_bytes(detectors, bands, levels))
+
+
+def rc_correct_ws(dn, lut, lines, detectors, bands, levels, out, ws, ws_bytes, plan=None,
+                  stream=None):
+    _check(_lib.rc_correct_ws(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out),
+                              _ptr(ws), ws_bytes, ctypes.byref(plan) if plan is not None else None,
+                              _stream(stream)), "rc_correct_ws")
 
 
 def rc_stream_copy(src, dst, nbytes, plan=None, stream=None):

@@ -225,11 +225,16 @@ void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t level
     const int64_t cus = std::max(1, di.cus);
     const size_t cu_budget = std::min(di.lds ? di.lds : (size_t)65536,
                                       di.lds_per_cu ? di.lds_per_cu : (size_t)65536);
-    // Long LUT rows (2048 <= L <= 8192): dense strips of up to 256 detectors
-    // (512-byte line segments) in one 160 KiB tile per CU, 512 threads, line
-    // chunks so that about one tile per CU runs.
+    // Long LUT rows (2048 <= L <= 8192) of a large scene: dense strips of up
+    // to 256 detectors (512-byte line segments) in one 160 KiB tile per CU,
+    // 512 threads, line chunks so that about one tile per CU runs. Each tile
+    // encodes its strip (W x L entries) before it streams, so only when a
+    // tile has at least 4 L lines to stream.
     const int wdense = std::min(256, widest_strip(RC_PATH_DENSE, levels, cu_budget));
-    if (levels >= 2048 && levels <= kDenseMaxLevels && wdense >= 64 && detectors >= 64) {
+    const int64_t dstrips = (detectors + wdense - 1) / std::max(wdense, 1);
+    const int64_t dtiles = std::max<int64_t>(1, cus / std::max<int64_t>(1, bands * dstrips));
+    if (levels >= 2048 && levels <= kDenseMaxLevels && wdense >= 64 && detectors >= 64 &&
+        lines / dtiles >= 4 * (int64_t)levels) {
         rc_plan p;
         std::memset(&p, 0, sizeof(p));
         p.path = RC_PATH_DENSE;
@@ -250,7 +255,10 @@ void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t level
         return;
     }
     const double share = (double)bands * (double)detectors / (double)cus;
-    if (legacy.path == RC_PATH_L2 || share <= (double)legacy.strip) {
+    // One tile per CU stages a whole strip with few waves: worth it only when
+    // the strip then streams many lines (at least 4 L).
+    if (legacy.path == RC_PATH_L2 || share <= (double)legacy.strip ||
+        lines < 4 * (int64_t)levels) {
         *plan = legacy;
         return;
     }
@@ -310,6 +318,8 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
     int64_t tiles = 0;
     if (!mul_ok((int64_t)bands * strips, chunks, &tiles)) return RC_EINVAL;
     if (tiles * plan.threads >= ((int64_t)1 << 32) || tiles > INT32_MAX) return RC_EINVAL;
+    p->pre_planes = nullptr;
+    p->pre_heads = nullptr;
     p->lines = lines;
     p->detectors = detectors;
     p->levels = levels;
@@ -353,22 +363,92 @@ rc_status validate_correct(const uint16_t* dn, const uint16_t* lut, int64_t line
     return RC_OK;
 }
 
+}  // namespace
+
+bool ws_path(int32_t levels) { return levels >= 2048 && levels <= kDenseMaxLevels; }
+
+size_t dense_ws_bytes(int32_t detectors, int32_t bands, int32_t levels) {
+    const size_t n = (size_t)bands * (size_t)((levels + 63) / 64) * (size_t)detectors;
+    return ((n * 8 + 255) & ~(size_t)255) + ((n * 2 + 255) & ~(size_t)255);
+}
+
+// Plan of the pre-encoded dense correction (measured on the 3 x 50000 x
+// 6000, L = 4096 scene): strips of at most 256 detectors (line segments of
+// up to 512 bytes), cut in equal widths so that bands x strips x line chunks
+// comes close to the CU count with the fewest chunks that allow it (each
+// chunk copies its strip's encoded blocks, 160 KiB, nothing to encode), one
+// 160 KiB tile per CU, 256 threads with 8 pixels (16 bytes) x 4 lines per
+// lane and register set, lanes packed without gaps.
+void ws_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
+             const DeviceInfo& di, rc_plan* plan) {
+    const size_t cu_budget = std::min(di.lds ? di.lds : (size_t)65536,
+                                      di.lds_per_cu ? di.lds_per_cu : (size_t)65536);
+    rc_plan p;
+    std::memset(&p, 0, sizeof(p));
+    p.path = RC_PATH_DENSE;
+    p.vec = std::min(vmax, 8);
+    p.threads = 256;
+    p.unroll = p.vec == 8 ? 4 : 8;
+    p.xcd_remap = 1;
+    p.lane_map = 1;
+    const int wmax = std::min(256, widest_strip(RC_PATH_DENSE, levels, cu_budget));
+    const int64_t cus = std::max(1, di.cus);
+    const int64_t units = detectors / p.vec;
+    const int64_t per = std::max(1, wmax / p.vec);
+    const int64_t smin = std::max<int64_t>(1, (units + per - 1) / per);
+    int64_t k = std::max<int64_t>(1, cus / std::max<int64_t>(1, (int64_t)bands * smin));
+    const int64_t cap = std::max<int64_t>(1, max_chunk_lines(detectors, p.threads, p.unroll));
+    k = std::max(k, (lines + cap - 1) / cap);
+    k = std::min<int64_t>(k, std::max<int64_t>(1, lines));
+    int64_t strips = std::max(smin, cus / std::max<int64_t>(1, (int64_t)bands * k));
+    strips = std::min(strips, units);
+    const int64_t widest = p.vec * ((units + strips - 1) / strips);
+    int W = 1;
+    while (W < widest) W <<= 1;
+    p.strip = W;
+    p.strips = (int32_t)strips;
+    p.chunk_lines = (int32_t)std::min<int64_t>((lines + k - 1) / k, INT32_MAX);
+    *plan = p;
+}
+
+namespace {
+
 rc_status run_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
                       int32_t bands, int32_t levels, uint16_t* out, const rc_plan* forced,
-                      hipStream_t stream) {
+                      hipStream_t stream, void* ws = nullptr, size_t ws_bytes = 0) {
     bool empty = false;
     rc_status st = validate_correct(dn, lut, lines, detectors, bands, levels, out, &empty);
     if (st != RC_OK || empty) return st;
+    const bool use_ws = ws != nullptr && ws_path(levels);
+    uint64_t* planes = nullptr;
+    int16_t* heads = nullptr;
+    if (use_ws) {
+        // The workspace holds the LUT's dense encoding: it may overlap none
+        // of the call's other buffers.
+        const size_t need = dense_ws_bytes(detectors, bands, levels);
+        if (ws_bytes < need || ((uintptr_t)ws & 255u)) return RC_EINVAL;
+        const size_t img = (size_t)lines * (size_t)detectors * (size_t)bands * 2;
+        const size_t lut_b = (size_t)bands * (size_t)detectors * (size_t)levels * 2;
+        if (overlaps(ws, need, dn, img) || overlaps(ws, need, out, img) ||
+            overlaps(ws, need, lut, lut_b))
+            return RC_EINVAL;
+        const size_t n = (size_t)bands * (size_t)((levels + 63) / 64) * (size_t)detectors;
+        planes = (uint64_t*)ws;
+        heads = (int16_t*)((char*)ws + ((n * 8 + 255) & ~(size_t)255));
+    }
     const DeviceInfo* di = current_device();
     if (!di) return RC_EHIP;
     const int vmax = max_vec(dn, out, detectors, 8);
     rc_plan plan;
     if (forced) {
         plan = *forced;
+    } else if (use_ws) {
+        ws_plan(lines, detectors, bands, levels, vmax, *di, &plan);
     } else if (!tuned_plan(lines, detectors, bands, levels, vmax, *di, &plan)) {
         default_plan(lines, detectors, bands, levels, vmax, *di, &plan);
     }
-    ApplyParams p;
+    if (use_ws && plan.path != RC_PATH_DENSE) return RC_EINVAL;
+    ApplyParams p{};
     size_t lds_bytes = 0;
     st = check_plan(plan, lines, detectors, bands, levels, vmax, *di, &p, &lds_bytes);
     if (st != RC_OK) return st;
@@ -376,6 +456,12 @@ rc_status run_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, in
     p.lut = lut;
     p.out = out;
     p.lut_vec = (levels % 8 == 0 && ((uintptr_t)lut & 15u) == 0) ? 1 : 0;
+    if (use_ws) {
+        hipError_t e = launch_dense_encode(lut, bands, detectors, levels, planes, heads, stream);
+        if (e != hipSuccess) return hip_fail(e);
+        p.pre_planes = planes;
+        p.pre_heads = heads;
+    }
     // When the tiles fit in a few rounds of one tile per CU, cap the tiles
     // resident per CU at ceil(tiles / CUs) through the LDS request, so the
     // dispatcher spreads them over every CU instead of stacking two on some
@@ -441,6 +527,18 @@ rc_status rc_correct_plan(const uint16_t* dn, const uint16_t* lut, int64_t lines
                           const rc_plan* plan, hipStream_t stream) {
     if (!plan) return RC_EINVAL;
     return run_correct(dn, lut, lines, detectors, bands, levels, out, plan, stream);
+}
+
+size_t rc_correct_ws_bytes(int32_t detectors, int32_t bands, int32_t levels) {
+    if (detectors <= 0 || bands <= 0 || !ws_path(levels)) return 0;
+    return dense_ws_bytes(detectors, bands, levels);
+}
+
+rc_status rc_correct_ws(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                        int32_t bands, int32_t levels, uint16_t* out, void* ws, size_t ws_bytes,
+                        const rc_plan* plan, hipStream_t stream) {
+    if (ws_path(levels) && detectors > 0 && bands > 0 && lines > 0 && !ws) return RC_EINVAL;
+    return run_correct(dn, lut, lines, detectors, bands, levels, out, plan, stream, ws, ws_bytes);
 }
 
 rc_status rc_plan_for(int64_t lines, int32_t detectors, int32_t bands, int32_t levels,

@@ -354,6 +354,37 @@ __device__ __forceinline__ bool dense_encode(const uint32_t (&e)[32], int n, uin
 // word (a plane's bit 0 is always 0; when the flag is set the tile does not
 // decode the strip). Call after every thread has staged; every thread returns
 // the same value.
+// Encodes block `blk` of LUT row `row` (L levels) into *plane and *head; a
+// block that does not fit the dense form gets bit 0 of its plane set.
+__device__ __forceinline__ void dense_encode_row_block(const uint16_t* row, int L, int blk,
+                                                      bool vec16, uint64_t* plane, int16_t* head) {
+    const uint16_t* src = row + (size_t)blk * 64;
+    const int cnt = min(64, L - blk * 64);
+    uint32_t e[32];
+    if (vec16 && cnt == 64) {
+#pragma unroll
+        for (int q4 = 0; q4 < 8; ++q4) {
+            const u32x4 w = *(const u32x4*)(src + q4 * 8);
+            e[q4 * 4 + 0] = w.x;
+            e[q4 * 4 + 1] = w.y;
+            e[q4 * 4 + 2] = w.z;
+            e[q4 * 4 + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const uint32_t a = 2 * k < cnt ? src[2 * k] : 0u;
+            const uint32_t c = 2 * k + 1 < cnt ? src[2 * k + 1] : 0u;
+            e[k] = a | (c << 16);
+        }
+    }
+    uint64_t pl = 0;
+    int16_t hd = 0;
+    if (!dense_encode(e, cnt, (uint32_t)(L - 1), &pl, &hd)) pl |= 1u;
+    *plane = pl;
+    *head = hd;
+}
+
 __device__ __forceinline__ int dense_any(int flag, uint64_t* planes) {
     __syncthreads();
     if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr((unsigned int*)planes, 1u);
@@ -391,7 +422,9 @@ template <int VEC, int UNROLL, int NT, int MODE>
 __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* __restrict__ lut,
                                            uint16_t* out, int64_t N, int D, int L, int logW,
                                            int b, int d0, int weff, int64_t n0, int64_t n1,
-                                           void* smem, bool lut_vec, bool dense) {
+                                           void* smem, bool lut_vec, bool dense,
+                                           const uint64_t* pre_planes = nullptr,
+                                           const int16_t* pre_heads = nullptr) {
     constexpr int LOGVEC = log_vec<VEC>();
     const int W = 1 << logW;
     const int tid = threadIdx.x;
@@ -481,10 +514,26 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
         uint64_t* planes = (uint64_t*)smem;
         int16_t* heads = (int16_t*)(planes + (size_t)NB * W);
         int bad = 0;
+        if (pre_planes) {
+            // Stage the blocks k_dense_encode wrote ([band][block][detector]):
+            // consecutive threads read consecutive detectors of one block.
+            const int items = NB * weff;
+            const size_t row0 = (size_t)b * (size_t)NB * (size_t)D + (size_t)d0;
+            for (int it = tid; it < items; it += nt) {
+                const int blk = it / weff;
+                const int jj = it - blk * weff;
+                const size_t g = row0 + (size_t)blk * (size_t)D + (size_t)jj;
+                const uint64_t pl = pre_planes[g];
+                const int p = ((jj & (VEC - 1)) << logq) + (jj >> LOGVEC);
+                bad |= (int)(pl & 1u);
+                planes[(blk << logW) + p] = pl;
+                heads[(blk << logW) + p] = pre_heads[g];
+            }
+        }
         // Stage: one lane encodes one block (detector jj, 64 levels); a wave
         // covers 64 consecutive LDS positions of one block index, so its
         // plane and header writes are consecutive words.
-        const int units = NB << logW;
+        const int units = pre_planes ? 0 : NB << logW;
         for (int u = tid; u < units; u += nt) {
             const int blk = u >> logW;
             const int p = u & (W - 1);

@@ -32,7 +32,18 @@ struct ApplyParams {
     int32_t xcds;        // 0/1: identity tile order, else the XCD count
     int32_t chunk_major; // 0: strips vary fastest, 1: line chunks vary fastest
     int32_t lut_vec;     // LUT rows may be staged with 16-byte loads
+    // Dense tiles: the strip's blocks already encoded by k_dense_encode
+    // (layout [bands][blocks][detectors]); NULL: each tile encodes its strip.
+    const uint64_t* pre_planes;
+    const int16_t* pre_heads;
 };
+
+// Encodes every 64-level block of every LUT row into the dense form (planes
+// and headers, [bands][ceil(levels / 64)][detectors]; a block that does not
+// fit the form gets bit 0 of its plane set).
+hipError_t launch_dense_encode(const uint16_t* lut, int32_t bands, int32_t detectors,
+                               int32_t levels, uint64_t* planes, int16_t* heads,
+                               hipStream_t stream);
 
 // lut_build: one thread per 8 consecutive levels of one LUT row.
 hipError_t launch_lut_build(const double* coeffs, int64_t rows, int32_t levels, uint16_t* lut,

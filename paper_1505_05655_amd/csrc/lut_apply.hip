@@ -43,7 +43,25 @@ __global__ __launch_bounds__(1024) void k_apply(ApplyParams p) {
     const int64_t n1 = min(p.lines, n0 + p.chunk_lines);
     apply_tile<VEC, UNROLL, NT, MODE>(p.dn, p.lut, p.out, p.lines, p.detectors, p.levels,
                                        p.log_strip, b, d0, weff, n0, n1, smem, p.lut_vec != 0,
-                                       p.dense != 0);
+                                       p.dense != 0, p.pre_planes, p.pre_heads);
+}
+
+// One thread per (row, 64-level block); consecutive threads take consecutive
+// blocks of a row (coalesced 16-byte LUT loads). Output [band][block][detector].
+__global__ __launch_bounds__(256) void k_dense_encode(const uint16_t* __restrict__ lut,
+                                                      int64_t rows, int32_t detectors,
+                                                      int32_t levels, uint64_t* planes,
+                                                      int16_t* heads, int32_t vec16) {
+    const int NB = (levels + 63) >> 6;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * NB) return;
+    const int64_t row = t / NB;
+    const int blk = (int)(t - row * NB);
+    const int64_t b = row / detectors;
+    const int64_t d = row - b * detectors;
+    const size_t o = ((size_t)b * NB + (size_t)blk) * (size_t)detectors + (size_t)d;
+    dense_encode_row_block(lut + (size_t)row * (size_t)levels, levels, blk, vec16 != 0,
+                           planes + o, heads + o);
 }
 
 typedef void (*ApplyKernel)(ApplyParams);
@@ -133,6 +151,18 @@ hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
             }
     *usable = dyn;
     return hipSuccess;
+}
+
+hipError_t launch_dense_encode(const uint16_t* lut, int32_t bands, int32_t detectors,
+                               int32_t levels, uint64_t* planes, int16_t* heads,
+                               hipStream_t stream) {
+    const int64_t rows = (int64_t)bands * detectors;
+    const int64_t items = rows * ((levels + 63) / 64);
+    if (items <= 0) return hipSuccess;
+    const int vec16 = (levels % 8 == 0 && ((uintptr_t)lut & 15u) == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_dense_encode, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, stream,
+                       lut, rows, detectors, levels, planes, heads, vec16);
+    return hipGetLastError();
 }
 
 hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_bytes,

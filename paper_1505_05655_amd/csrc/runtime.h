@@ -50,6 +50,13 @@ bool balanced_tiling(int64_t lines, int32_t detectors, int32_t bands, int vec, i
 // Widest power-of-two strip (<= 1024 detectors) whose LDS tile fits `budget`.
 int widest_strip(int path, int levels, size_t budget);
 
+// Levels for which rc_correct_ws encodes the LUT into its workspace, the
+// workspace bytes that takes, and the plan it runs with.
+bool ws_path(int32_t levels);
+size_t dense_ws_bytes(int32_t detectors, int32_t bands, int32_t levels);
+void ws_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
+             const DeviceInfo& di, rc_plan* plan);
+
 // Default launch shape for a shape class (no tuning).
 void default_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
                   const DeviceInfo& di, rc_plan* plan);

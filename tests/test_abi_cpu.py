@@ -250,3 +250,13 @@ def test_plan_cache_file_roundtrip(tmp_path):
         assert rc.rc_tune_count() == 0
     finally:
         rc.rc_tune_load(None)  # back to the packaged cache
+
+
+def test_ws_bytes_host():
+    """Workspace size of rc_correct_ws (host only): 10 bytes per 64-level
+    block of every LUT row for 2048 <= levels <= 8192, in 256-byte pieces."""
+    assert rc.rc_correct_ws_bytes(6000, 3, 4096) == 3 * 64 * 6000 * 8 + 3 * 64 * 6000 * 2
+    assert rc.rc_correct_ws_bytes(7, 1, 2048) == 1792 + 512  # 224 blocks: 1792 B + 448 B -> 512
+    assert rc.rc_correct_ws_bytes(100, 2, 1024) == 0
+    assert rc.rc_correct_ws_bytes(100, 2, 8193) == 0
+    assert rc.rc_correct_ws_bytes(0, 2, 4096) == 0

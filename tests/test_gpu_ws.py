@@ -1,0 +1,96 @@
+"""rc_correct_ws (the LUT encoded once into a workspace, then the dense
+correction) against the oracle, bit-exact: long and short LUT rows,
+calibration-like, saturating and unpackable rows, forced plans, and the
+workspace checks."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1505_05655_amd as rc
+import pins
+from gpu_util import Guarded, dev, to_dev_f64, to_dev_u16
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.get()
+
+
+def case(shape, rows, seed):
+    B, N, D, L = shape
+    coeffs, dn = pins.tiny_case(seed, B, N, D, L)
+    rng = np.random.default_rng(seed)
+    coeffs[..., 0] = rng.normal(0, L / 128, size=(B, D))
+    coeffs[..., 1] = rng.uniform(0.9, 1.1, size=(B, D))
+    coeffs[..., 2] = rng.normal(0, 0.05 / L, size=(B, D))
+    coeffs[..., 3] = rng.normal(0, 0.01 / L ** 2, size=(B, D))
+    if rows == "clamped":
+        coeffs[..., 0] = rng.uniform(-L / 4, L / 4, size=(B, D))
+        coeffs[..., 1] = rng.uniform(0.6, 1.6, size=(B, D))
+    if rows == "unpackable":
+        coeffs[0, D // 2] = [L - 1, -1.0, 0, 0]
+        coeffs[-1, D - 1] = [L / 3, 1.0, 3.0 / L, 0]
+    return coeffs, dn
+
+
+SHAPES = [(3, 401, 1000, 4096), (1, 300, 520, 2048), (2, 77, 96, 8192), (1, 129, 333, 3000),
+          (2, 64, 200, 1024), (1, 5, 7, 4096)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("rows", ["calibration", "clamped", "unpackable"])
+def test_ws_matches_oracle(o, shape, rows):
+    B, N, D, L = shape
+    coeffs, dn = case(shape, rows, B * 7 + N + D + L)
+    lut = o.lut_build(coeffs, L)
+    want = o.correct(dn, lut)
+    lut_t = rc.lut_build(to_dev_f64(coeffs), L)
+    dn_t = to_dev_u16(dn)
+    need = rc.rc_correct_ws_bytes(D, B, L)
+    assert need == (0 if L < 2048 else
+                    ((B * -(-L // 64) * D * 8 + 255) // 256 * 256 +
+                     (B * -(-L // 64) * D * 2 + 255) // 256 * 256))
+    ws = torch.full((max(need, 256) // 2 + 128,), 0x3C3C, dtype=torch.int16, device=dev())
+    plans = [None]
+    if L >= 2048:
+        for strip, vec, threads, unroll, chunk, strips in ((256, 4, 512, 8, N, 0),
+                                                           (128, 8, 256, 4, 17, 0),
+                                                           (64, 2, 1024, 16, 5, 0),
+                                                           (256, 4, 256, 8, 33, 3)):
+            if D % vec or -(-L // 64) * strip * 10 > 160 * 1024:
+                continue
+            if strips and (strips > D // vec or vec * -(-(D // vec) // strips) > strip):
+                continue
+            plans.append(rc.Plan(path=rc.RC_PATH_DENSE, strip=strip, vec=vec, threads=threads,
+                                 unroll=unroll, chunk_lines=chunk, xcd_remap=1, nontemporal=0,
+                                 strips=strips))
+    for plan in plans:
+        out = Guarded((B, N, D))
+        rc.rc_correct_ws(dn_t, lut_t, N, D, B, L, out.t, ws, need, plan)
+        torch.cuda.synchronize()
+        out.check_pads()
+        assert np.array_equal(out.host(), want), f"plan {plan}"
+
+
+def test_ws_rejects():
+    B, N, D, L = 1, 8, 64, 4096
+    dn = torch.zeros((B, N, D), dtype=torch.int16, device=dev())
+    lut = torch.zeros((B, D, L), dtype=torch.int16, device=dev())
+    out = torch.empty_like(dn)
+    need = rc.rc_correct_ws_bytes(D, B, L)
+    ws = torch.empty(need // 2 + 1024, dtype=torch.int16, device=dev())
+    for args in ((ws, need - 256), (None, need), (ws[1:], need)):
+        with pytest.raises(rc.RcError) as e:
+            rc.rc_correct_ws(dn, lut, N, D, B, L, out, args[0], args[1])
+        assert e.value.status == rc.RC_EINVAL
+    # Overlapping the image, and a plan that is not dense.
+    big = torch.zeros(need // 2 + B * N * D + 1024, dtype=torch.int16, device=dev())
+    with pytest.raises(rc.RcError):
+        rc.rc_correct_ws(big[:B * N * D], lut, N, D, B, L, out, big, need)
+    bad = rc.Plan(path=rc.RC_PATH_PACKED, strip=64, vec=2, threads=256, unroll=4, chunk_lines=4,
+                  xcd_remap=1, nontemporal=0)
+    with pytest.raises(rc.RcError):
+        rc.rc_correct_ws(dn, lut, N, D, B, L, out, ws, need, bad)
