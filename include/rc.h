@@ -208,6 +208,26 @@ rc_status rc_correct_ws(const uint16_t* dn, const uint16_t* lut, int64_t lines, 
                         int32_t bands, int32_t levels, uint16_t* out, void* ws, size_t ws_bytes,
                         const rc_plan* plan, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * correction of rc_correct_ws with the library's own scratch instead of a
+ * workspace argument. The scratch is a device array of
+ * RC_NOALLOC_SCRATCH_BYTES per GPU, held by the library until the process
+ * ends; this call allocates nothing (no hipMalloc, no allocating library
+ * routine) and never synchronises. Shapes that rc_correct_ws runs without a
+ * workspace run as rc_correct. RC_EINVAL when the shape needs more scratch
+ * than RC_NOALLOC_SCRATCH_BYTES (rc_correct_ws_bytes(...) > the maximum),
+ * otherwise errors as rc_correct_ws. Every call on one GPU shares its
+ * scratch: calls that overlap on one GPU (different streams, or threads
+ * without ordering) race and give wrong results; calls ordered on one stream
+ * are safe.
+ */
+#define RC_NOALLOC_SCRATCH_BYTES (32u << 20)
+rc_status rc_correct_noalloc(const uint16_t* dn, const uint16_t* lut, int64_t lines,
+                             int32_t detectors, int32_t bands, int32_t levels, uint16_t* out,
+                             hipStream_t stream);
+
 /* ---- least-squares calibration fit ---------------------------------------------------- */
 
 /*

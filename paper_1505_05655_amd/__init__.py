@@ -184,6 +184,9 @@ _lib.rc_correct_ws_bytes.restype = ctypes.c_size_t
 _lib.rc_correct_ws.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t,
                                ctypes.POINTER(Plan), _vp]
 _lib.rc_correct_ws.restype = ctypes.c_int
+_lib.rc_correct_noalloc.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp]
+_lib.rc_correct_noalloc.restype = ctypes.c_int
+NOALLOC_SCRATCH_BYTES = 32 << 20
 _lib.rc_stream_copy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(CopyPlan), _vp]
 _lib.rc_stream_copy.restype = ctypes.c_int
 _lib.rc_host_alloc.argtypes = [ctypes.c_size_t]
@@ -261,6 +264,12 @@ def rc_correct_ws(dn, lut, lines, detectors, bands, levels, out, ws, ws_bytes, p
     _check(_lib.rc_correct_ws(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out),
                               _ptr(ws), ws_bytes, ctypes.byref(plan) if plan is not None else None,
                               _stream(stream)), "rc_correct_ws")
+
+
+def rc_correct_noalloc(dn, lut, lines, detectors, bands, levels, out, stream=None):
+    """rc_correct_ws with the library's scratch (allocates nothing; see rc.h)."""
+    _check(_lib.rc_correct_noalloc(_ptr(dn), _ptr(lut), lines, detectors, bands, levels,
+                                   _ptr(out), _stream(stream)), "rc_correct_noalloc")
 
 
 def rc_stream_copy(src, dst, nbytes, plan=None, stream=None):

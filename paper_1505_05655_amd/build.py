@@ -22,8 +22,8 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC]
 SOURCES = ["lut_build.hip", "lut_apply.hip", "batch.hip", "fit.hip", "demosaic.hip",
-           "demosaic_gradient.hip", "stream_copy.hip", "api.cpp", "tune.cpp", "serve.cpp",
-           "wire.cpp"]
+           "demosaic_gradient.hip", "stream_copy.hip", "noalloc.hip", "api.cpp", "tune.cpp",
+           "serve.cpp", "wire.cpp"]
 
 
 def _compile(src):
