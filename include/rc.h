@@ -112,7 +112,7 @@ typedef struct {
                             for W detectors */
     int32_t vec;         /* pixels per lane per line: 1, 2, 4 or 8 (8: 16-byte image accesses,
                             needs detectors % 8 == 0 and 16-byte aligned dn and out) */
-    int32_t threads;     /* workgroup size: 256, 512 or 1024 */
+    int32_t threads;     /* workgroup size: 256, 512 or 1024 (RC_PATH_DENSE: 256 or 512) */
     int32_t unroll;      /* lines in flight per lane: 4, 8 or 16 */
     int32_t chunk_lines; /* lines per tile, >= 1 */
     int32_t xcd_remap;   /* 1: place neighbouring tiles on the same XCD */

@@ -290,6 +290,7 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
         plan.path != RC_PATH_DENSE)
         return RC_EINVAL;
     if (plan.path == RC_PATH_DENSE && levels > kDenseMaxLevels) return RC_EINVAL;
+    if (plan.path == RC_PATH_DENSE && plan.threads > kDenseMaxThreads) return RC_EINVAL;
     if (!is_pow2(plan.strip) || plan.strip > 1024) return RC_EINVAL;
     if (plan.vec != 1 && plan.vec != 2 && plan.vec != 4 && plan.vec != 8) return RC_EINVAL;
     if (plan.vec > vmax || plan.strip < plan.vec) return RC_EINVAL;
@@ -334,6 +335,15 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
     p->ntiles = (int32_t)tiles;
     p->xcds = plan.xcd_remap ? di.xcds : 1;
     p->chunk_major = plan.path == RC_PATH_L2 ? 1 : 0;
+    // LDS tiles interleave their line chunks pass by pass (measured on the
+    // 3 x 50000 x 6000 scene: the tiles of neighbouring strips and chunks
+    // then stream neighbouring lines together, 3 % faster than contiguous
+    // chunks) when a whole band, plus the prefetch overshoot of a tile that
+    // steps `chunks` passes at a time, stays within the 32-bit offsets.
+    p->interleave = (plan.path != RC_PATH_L2 && chunks > 1 &&
+                     lines + 2 * (chunks - 1) * (int64_t)plan.threads * plan.unroll <=
+                         max_chunk_lines(detectors, plan.threads, plan.unroll))
+                        ? 1 : 0;
     *lds_bytes = bytes;
     return RC_OK;
 }

@@ -163,7 +163,9 @@ template <int NT> struct Buf<8, NT> {
 };
 
 // Streams `passes` passes over a tile's lines. In each pass a lane handles
-// its VEC pixels of UNROLL lines (line_stride bytes apart). Software
+// its VEC pixels of UNROLL lines (line_stride bytes apart); consecutive
+// passes start pass_adv bytes apart (0: UNROLL * line_stride, contiguous
+// lines; a multiple of it when a tile takes every k-th pass). Software
 // pipelined with two register sets used alternately: the loads of pass k+1
 // are issued before pass k is gathered and stored, so a wave's memory
 // latency overlaps its own gather work (no register copies between the sets,
@@ -173,14 +175,16 @@ template <int NT> struct Buf<8, NT> {
 template <int VEC, int UNROLL, int NT, typename G>
 __device__ __forceinline__ void stream_lines(__amdgpu_buffer_rsrc_t rin,
                                              __amdgpu_buffer_rsrc_t rout, uint32_t vo,
-                                             uint32_t line_stride, int passes, G gather) {
+                                             uint32_t line_stride, int passes, G gather,
+                                             uint32_t pass_adv = 0) {
     typedef typename Px<VEC>::T T;
-    const uint32_t pass_bytes = UNROLL * line_stride;
+    const uint32_t pass_bytes = pass_adv ? pass_adv : UNROLL * line_stride;
     T a[UNROLL], b[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) a[u] = Buf<VEC, NT>::ld(rin, vo, u * line_stride);
-    uint32_t so = 0;
+    uint32_t so = 0;  // wave-uniform line offset of the current pass
     for (int k = 0; k < passes; k += 2) {
+        so = __builtin_amdgcn_readfirstlane(so);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
             b[u] = Buf<VEC, NT>::ld(rin, vo, so + pass_bytes + u * line_stride);
@@ -244,45 +248,82 @@ __host__ __device__ constexpr size_t packed_lds_bytes(int W, int L) {
 
 // ---- dense LDS strip: one bit per step -------------------------------------------------
 //
-// A LUT row is cut into blocks of 64 levels. Within a block the entries
+// A LUT row is cut into blocks of 64 levels. Within block `blk` the entries
 // e_0..e_63 are stored as an unclamped staircase U_0..U_63 with
 // clamp(U_i, 0, L-1) = e_i:
-//   U_i = base + s*i + (number of t < i with bit t+1 of the plane set),
-// i.e. each step U_{t+1} - U_t is s or s + 1 (s = 0..3, the block's slope)
-// and bit t+1 of a 64-bit plane says which (bit 0 stays 0). A 16-bit header
-// holds (base << 2) | s. Where the row saturates (entries 0 before the first
-// positive one, entries L-1 from the first L-1 on) the staircase goes on
-// below 0 / above L-1 in steps of s + 1 and the clamp restores the entries.
-// For i = v mod 64:
-//   entry(v) = med3(base + s*i + popcount(plane << (63 - i)), 0, L-1),
-// exactly. 80 bits per 64 entries (1.25 bits per entry): a 4096-level strip
-// of 256 detectors fits 160 KiB. Encodable blocks: non-decreasing, with the
-// steps between unsaturated entries within {s, s+1}, s <= 3 (calibration
-// LUTs: gains near 1); other rows make the tile gather from the global LUT.
-// Layout: planes [NB][W] (64-bit) then headers [NB][W] (int16), detector j
-// of the strip at position p = (j % VEC) * (W / VEC) + j / VEC, as the packed
-// strip. Requires L <= kDenseMaxLevels = 8192 (header range).
+//   U_i = U_0 + s*i + sum_{t<i} b_t,   s in {0, 1},  b_t in {0, 1},
+// i.e. each step U_{t+1} - U_t is s or s + 1. Where the row saturates
+// (entries 0 before the first positive one, entries L-1 from the first L-1
+// on) the staircase goes on below 0 / above L-1 in steps of s + 1 and the
+// clamp restores the entries. The encoder takes s = max(0, largest step -
+// 1), so a block whose only unsaturated step is 2 (a jump into or out of a
+// saturated run) still fits.
+//
+// Stored form, chosen so that the decode is additive and needs no masks:
+//   plane z: bit 63 - t = 1 - b_t (t = 0..62), bit 0 = s;
+//   header H (int16) = U_0 + B - 63 - 64*(s+1)*blk - s,  B = sum_t b_t.
+// Shifting z left by i keeps bits 0..63-i, i.e. the complemented steps
+// t >= i and bit 0, so popcount(z << i) = (63 - i) - sum_{t>=i} b_t + s and,
+// with m = s + 1 and level v = 64*blk + i,
+//   U = H + m*v + popcount(z << (v mod 64))      (m*v = v << s),
+// exactly. |H| < 16448 for L <= 8192, so H never equals kDenseBad, the
+// header that marks a block the dense form cannot hold. 80 bits per 64
+// entries (1.25 bits per entry): a 4096-level strip of 256 detectors fits
+// 160 KiB. Encodable blocks: non-decreasing, with the steps between
+// unsaturated entries within {s, s+1}, s <= 1 (calibration LUTs: gains
+// below 2); other rows make the tile gather from the global LUT.
+// Layout: headers [NB][W] (int16) from byte 0, planes [NB][W] (64-bit) from
+// byte kDenseHeads = 32 KiB (a tile's NB x W blocks never exceed 16384 in
+// 160 KiB), detector j of the strip at position p = (j % VEC) * (W / VEC) +
+// j / VEC, as the packed strip. Requires L <= kDenseMaxLevels = 8192
+// (header range).
+constexpr int kDenseHeads = 32768;
+constexpr int16_t kDenseBad = -32768;
 
 __host__ __device__ constexpr size_t dense_lds_bytes(int W, int L) {
-    return (size_t)((L + 63) / 64) * (size_t)W * 10;
+    return (size_t)kDenseHeads + (size_t)((L + 63) / 64) * (size_t)W * 8;
 }
 
-__device__ __forceinline__ uint32_t g_dense(const uint64_t* planes, const int16_t* heads,
-                                            uint32_t dnv, uint32_t top, int logW, int p) {
+// LDS addressed from byte 0: the correction kernels have no static LDS, so
+// their dynamic LDS starts at 0 (prepare_apply_kernels checks it on the host
+// and refuses the dense mode otherwise); with the base a known constant no
+// address needs an add for it.
+typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+typedef __attribute__((address_space(3))) const int16_t lds_i16;
+
+// med3(x, 0, hi) in one instruction (the compiler forms it only for
+// constant bounds); hi is wave-uniform.
+__device__ __forceinline__ uint32_t clamp0(int x, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return (uint32_t)r;
+}
+
+// popcount(x) + acc in one instruction (the compiler would otherwise sum
+// two popcounts with a separate three-way add).
+__device__ __forceinline__ int bcnt_acc(uint32_t x, int acc) {
+    int r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+// p8 = 8 * p (the lane's position, in bytes of the plane array).
+__device__ __forceinline__ uint32_t g_dense(uint32_t dnv, uint32_t top, int logW, uint32_t p8) {
     const uint32_t v = dnv < top ? dnv : top;
-    const int idx = (int)((v >> 6) << logW) + p;
-    const uint64_t pl = planes[idx];
-    const int h = heads[idx];
-    const uint64_t sh = pl << ((~v) & 63u);  // keeps plane bits 0..i, i = v mod 64
-    const int c = __builtin_popcount((uint32_t)sh) + __builtin_popcount((uint32_t)(sh >> 32));
-    const int u = (h >> 2) + (h & 3) * (int)(v & 63u) + c;
-    return (uint32_t)min(max(u, 0), (int)top);
+    const uint32_t a8 = ((v >> 6) << (logW + 3)) + p8;  // 8 x block index
+    const uint64_t z = *(lds_u64*)(uintptr_t)(kDenseHeads + a8);
+    const int h = *(lds_i16*)(uintptr_t)(a8 >> 2);
+    const uint64_t sh = z << (v & 63u);
+    int u = (int)(v << ((uint32_t)z & 1u)) + h;
+    u = bcnt_acc((uint32_t)(sh >> 32), u);
+    u = bcnt_acc((uint32_t)sh, u);
+    return clamp0(u, (int)top);
 }
 
-// Encodes one block of `n` entries (1..64) of a LUT row: e holds the entries
+// Encodes block `blk` (n entries, 1..64) of a LUT row: e holds the entries
 // two per word (entry 2k in the low half of e[k]). Returns false when the
 // block is not encodable.
-__device__ __forceinline__ bool dense_encode(const uint32_t (&e)[32], int n, uint32_t top,
+__device__ __forceinline__ bool dense_encode(const uint32_t (&e)[32], int n, uint32_t top, int blk,
                                              uint64_t* plane, int16_t* head) {
     auto at = [&](int i) -> int { return (int)((e[i >> 1] >> ((i & 1) * 16)) & 0xffffu); };
     // Pass 1: smallest and largest step.
@@ -297,16 +338,19 @@ __device__ __forceinline__ bool dense_encode(const uint32_t (&e)[32], int n, uin
     }
     if (n > 1 && mn < 0) return false;  // decreasing somewhere
     const int e0 = at(0), elast = at(n - 1);
+    // b: bit t+1 = b_t (the step-minus-slope bits, t = 0..62).
     uint32_t lo = 0, hi = 0;
-    int s = 0, base = 0;
+    int s = 0, u0 = 0;
     if (n == 1 || e0 == (int)top || elast == 0) {
         // Constant (a single entry, all L-1, or all 0 in a non-decreasing block).
-        base = e0;
+        u0 = e0;
     } else if (e0 != 0 && elast != (int)top) {
-        // No saturated entry (non-decreasing, 0 < e0, e_last < L-1).
-        s = mn;
-        if (s > 3 || mx > s + 1) return false;
-        base = e0;
+        // No saturated entry (non-decreasing, 0 < e0, e_last < L-1). Any
+        // s in [mx - 1, mn] holds the steps; the largest keeps s <= 1 for
+        // the most blocks.
+        s = max(0, mx - 1);
+        if (s > 1 || mn < s) return false;
+        u0 = e0;
 #pragma unroll
         for (int t = 0; t < 63; ++t) {
             if (t + 1 < n) {
@@ -331,10 +375,10 @@ __device__ __forceinline__ bool dense_encode(const uint32_t (&e)[32], int n, uin
                 if (a == 0 && b != 0 && first == n) first = t + 1;
             }
         }
-        s = smin > 3 ? 4 : smin;
-        if (s > 3 || smax > s + 1) return false;
+        s = max(0, smax - 1);
+        if (s > 1 || smin < s) return false;
         // U_{first-1} = 0 when the block opens with a run of 0.
-        base = e0 != 0 ? e0 : -(s + 1) * (first - 1);
+        u0 = e0 != 0 ? e0 : -(s + 1) * (first - 1);
 #pragma unroll
         for (int t = 0; t < 63; ++t) {
             if (t + 1 < n) {
@@ -345,17 +389,18 @@ __device__ __forceinline__ bool dense_encode(const uint32_t (&e)[32], int n, uin
             }
         }
     }
-    *plane = ((uint64_t)hi << 32) | lo;
-    *head = (int16_t)((base << 2) | s);
+    const uint64_t bits = ((uint64_t)hi << 32) | lo;
+    // Bit t+1 of `bits` -> bit 63-t, complemented; bit 0 <- s.
+    const uint64_t z = (~(__builtin_bitreverse64(bits) << 1) & ~(uint64_t)1) | (uint64_t)s;
+    const int H = u0 + __builtin_popcountll(bits) - 63 - 64 * (s + 1) * blk - s;
+    if (H <= (int)kDenseBad || H > 32767) return false;
+    *plane = z;
+    *head = (int16_t)H;
     return true;
 }
 
-// Workgroup-wide OR of `flag` for a dense strip, in bit 0 of the first plane
-// word (a plane's bit 0 is always 0; when the flag is set the tile does not
-// decode the strip). Call after every thread has staged; every thread returns
-// the same value.
 // Encodes block `blk` of LUT row `row` (L levels) into *plane and *head; a
-// block that does not fit the dense form gets bit 0 of its plane set.
+// block that does not fit the dense form gets the header kDenseBad.
 __device__ __forceinline__ void dense_encode_row_block(const uint16_t* row, int L, int blk,
                                                       bool vec16, uint64_t* plane, int16_t* head) {
     const uint16_t* src = row + (size_t)blk * 64;
@@ -379,17 +424,21 @@ __device__ __forceinline__ void dense_encode_row_block(const uint16_t* row, int 
         }
     }
     uint64_t pl = 0;
-    int16_t hd = 0;
-    if (!dense_encode(e, cnt, (uint32_t)(L - 1), &pl, &hd)) pl |= 1u;
+    int16_t hd = kDenseBad;
+    if (!dense_encode(e, cnt, (uint32_t)(L - 1), blk, &pl, &hd)) hd = kDenseBad;
     *plane = pl;
     *head = hd;
 }
 
-__device__ __forceinline__ int dense_any(int flag, uint64_t* planes) {
+// Workgroup-wide OR of `flag` for a dense strip, without static LDS: a
+// wave with the flag set writes kDenseBad (a header no encodable block has)
+// over the first header; the tile then does not decode the strip. Call
+// after every thread has staged; every thread returns the same value.
+__device__ __forceinline__ int dense_any(int flag, int16_t* heads) {
     __syncthreads();
-    if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr((unsigned int*)planes, 1u);
+    if (__any(flag) && (threadIdx.x & 63) == 0) heads[0] = kDenseBad;
     __syncthreads();
-    return (int)(*(const unsigned int*)planes & 1u);
+    return (int)(heads[0] == kDenseBad);
 }
 
 enum TileMode { kRaw = 0, kGlobal = 1, kPacked = 2, kDense = 3 };
@@ -424,7 +473,8 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
                                            int b, int d0, int weff, int64_t n0, int64_t n1,
                                            void* smem, bool lut_vec, bool dense,
                                            const uint64_t* pre_planes = nullptr,
-                                           const int16_t* pre_heads = nullptr) {
+                                           const int16_t* pre_heads = nullptr, int ci = 0,
+                                           int ck = 1) {
     constexpr int LOGVEC = log_vec<VEC>();
     const int W = 1 << logW;
     const int tid = threadIdx.x;
@@ -436,7 +486,9 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
     const int q = dense ? (weff >> LOGVEC) : (1 << logq);  // lanes per strip line
     const int row = tid / q;         // this thread's line within a pass
     const int lane = tid - row * q;
-    const int rpp = nt / q;          // lines per pass
+    // Wave-uniform (the compiler cannot prove it through the division and
+    // would otherwise wrap every buffer access in a waterfall loop).
+    const int rpp = __builtin_amdgcn_readfirstlane(nt / q);  // lines per pass
     // Threads past the last whole line, or past the strip, only stage.
     const bool streams = row < rpp && lane * VEC < weff;
     const int j = lane * VEC;
@@ -446,9 +498,16 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
     const uint32_t span = (uint32_t)((((size_t)(n1 - n0) - 1) * (size_t)D + (size_t)weff) * 2);
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(dn + tile0, span);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + tile0, span);
-    const uint32_t vo = (uint32_t)(((size_t)row * (size_t)D + (size_t)j) * 2);
+    // Passes of rpp x UNROLL lines over [n0, n1); the tile takes passes ci,
+    // ci + ck, ci + 2 ck, ... (ck = 1: all of them).
     const uint32_t line_stride = (uint32_t)rpp * (uint32_t)D * 2u;
-    const int passes = (int)((n1 - n0 + (int64_t)rpp * UNROLL - 1) / ((int64_t)rpp * UNROLL));
+    const uint32_t pass_bytes = UNROLL * line_stride;
+    const uint32_t pass_adv = pass_bytes * (uint32_t)ck;
+    const uint32_t vo = (uint32_t)(((size_t)row * (size_t)D + (size_t)j) * 2) +
+                        (uint32_t)ci * pass_bytes;
+    const int all_passes =
+        (int)((n1 - n0 + (int64_t)rpp * UNROLL - 1) / ((int64_t)rpp * UNROLL));
+    const int passes = ci < all_passes ? (all_passes - ci + ck - 1) / ck : 0;
 
     if constexpr (MODE == kRaw) {
         uint16_t* tile = (uint16_t*)smem;
@@ -499,7 +558,7 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
         if (streams) {
             stream_lines<VEC, UNROLL, NT>(
                 rin, rout, vo, line_stride, passes,
-                [&](int k, uint32_t d) { return g_raw(tile, d, top, logW, j + k); });
+                [&](int k, uint32_t d) { return g_raw(tile, d, top, logW, j + k); }, pass_adv);
         }
         __syncthreads();  // the tile may be restaged next
     } else if constexpr (MODE == kGlobal) {
@@ -507,12 +566,12 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
             const uint16_t* lrow = strip_lut + (size_t)j * Lz;
             stream_lines<VEC, UNROLL, NT>(
                 rin, rout, vo, line_stride, passes,
-                [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
+                [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); }, pass_adv);
         }
     } else if constexpr (MODE == kDense) {
         const int NB = (L + 63) >> 6;
-        uint64_t* planes = (uint64_t*)smem;
-        int16_t* heads = (int16_t*)(planes + (size_t)NB * W);
+        int16_t* heads = (int16_t*)smem;
+        uint64_t* planes = (uint64_t*)((unsigned char*)smem + kDenseHeads);
         int bad = 0;
         if (pre_planes) {
             // Stage the blocks k_dense_encode wrote ([band][block][detector]):
@@ -523,11 +582,11 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
                 const int blk = it / weff;
                 const int jj = it - blk * weff;
                 const size_t g = row0 + (size_t)blk * (size_t)D + (size_t)jj;
-                const uint64_t pl = pre_planes[g];
+                const int16_t hd = pre_heads[g];
                 const int p = ((jj & (VEC - 1)) << logq) + (jj >> LOGVEC);
-                bad |= (int)(pl & 1u);
-                planes[(blk << logW) + p] = pl;
-                heads[(blk << logW) + p] = pre_heads[g];
+                bad |= (int)(hd == kDenseBad);
+                planes[(blk << logW) + p] = pre_planes[g];
+                heads[(blk << logW) + p] = hd;
             }
         }
         // Stage: one lane encodes one block (detector jj, 64 levels); a wave
@@ -560,23 +619,23 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
                 }
             }
             uint64_t pl = 0;
-            int16_t hd = 0;
-            if (!dense_encode(e, cnt, top, &pl, &hd)) bad = 1;
+            int16_t hd = kDenseBad;
+            if (!dense_encode(e, cnt, top, blk, &pl, &hd)) bad = 1;
             planes[u] = pl;
             heads[u] = hd;
         }
-        bad = dense_any(bad, planes);
+        bad = dense_any(bad, heads);
         if (streams) {
             if (!bad) {
                 stream_lines<VEC, UNROLL, NT>(
                     rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
-                        return g_dense(planes, heads, d, top, logW, (k << logq) + lane);
-                    });
+                        return g_dense(d, top, logW, (uint32_t)((k << logq) + lane) * 8u);
+                    }, pass_adv);
             } else {
                 const uint16_t* lrow = strip_lut + (size_t)j * Lz;
                 stream_lines<VEC, UNROLL, NT>(
                     rin, rout, vo, line_stride, passes,
-                    [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
+                    [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); }, pass_adv);
             }
         }
         __syncthreads();  // the tile may be restaged next
@@ -701,12 +760,12 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
                 stream_lines<VEC, UNROLL, NT>(
                     rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
                         return g_packed(planes, bases, d, top, logW, (k << logq) + lane);
-                    });
+                    }, pass_adv);
             } else {
                 const uint16_t* lrow = strip_lut + (size_t)j * Lz;
                 stream_lines<VEC, UNROLL, NT>(
                     rin, rout, vo, line_stride, passes,
-                    [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); });
+                    [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); }, pass_adv);
             }
         }
         __syncthreads();  // the tile may be restaged next

@@ -10,6 +10,8 @@ namespace rc {
 
 // Longest LUT rows the dense LDS strip encodes (16-bit block headers).
 constexpr int kDenseMaxLevels = 8192;
+// Most threads per workgroup of the dense path (its kernels' launch bound).
+constexpr int kDenseMaxThreads = 512;
 
 // Everything the correction kernel needs to decode a tile id.
 struct ApplyParams {
@@ -31,6 +33,7 @@ struct ApplyParams {
     int32_t ntiles;      // bands * strips * chunks
     int32_t xcds;        // 0/1: identity tile order, else the XCD count
     int32_t chunk_major; // 0: strips vary fastest, 1: line chunks vary fastest
+    int32_t interleave;  // 1: line chunk c of `chunks` is every chunks-th pass from pass c
     int32_t lut_vec;     // LUT rows may be staged with 16-byte loads
     // Dense tiles: the strip's blocks already encoded by k_dense_encode
     // (layout [bands][blocks][detectors]); NULL: each tile encodes its strip.

@@ -11,8 +11,11 @@
 
 namespace rc {
 
+// The dense mode runs at most 512 threads (its 160 KiB tile allows one
+// workgroup per CU, two waves per SIMD): the tighter bound leaves it the
+// registers to keep every pixel's LDS reads of a register set in flight.
 template <int VEC, int UNROLL, int NT, int MODE>
-__global__ __launch_bounds__(1024) void k_apply(ApplyParams p) {
+__global__ __launch_bounds__(MODE == kDense ? kDenseMaxThreads : 1024) void k_apply(ApplyParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x, p.xcds);
     int s, c, b;
@@ -39,15 +42,28 @@ __global__ __launch_bounds__(1024) void k_apply(ApplyParams p) {
         d0 = s * W;
         weff = min(W, p.detectors - d0);
     }
-    const int64_t n0 = (int64_t)c * p.chunk_lines;
-    const int64_t n1 = min(p.lines, n0 + p.chunk_lines);
+    // Line chunk c: contiguous lines, or (interleaved) every chunks-th pass
+    // of the band's lines from pass c, so that the tiles of one strip read
+    // neighbouring lines at the same time.
+    int64_t n0 = 0, n1 = p.lines;
+    int ci = 0, ck = 1;
+    if (p.interleave) {
+        ci = c;
+        ck = p.chunks;
+    } else {
+        n0 = (int64_t)c * p.chunk_lines;
+        n1 = min(p.lines, n0 + p.chunk_lines);
+    }
     apply_tile<VEC, UNROLL, NT, MODE>(p.dn, p.lut, p.out, p.lines, p.detectors, p.levels,
                                        p.log_strip, b, d0, weff, n0, n1, smem, p.lut_vec != 0,
-                                       p.dense != 0, p.pre_planes, p.pre_heads);
+                                       p.dense != 0, p.pre_planes, p.pre_heads, ci, ck);
 }
 
-// One thread per (row, 64-level block); consecutive threads take consecutive
-// blocks of a row (coalesced 16-byte LUT loads). Output [band][block][detector].
+// One thread per (row, 64-level block). Consecutive threads take the same
+// block of consecutive rows: their output words are consecutive (output
+// [band][block][detector]), and a wave's blocks are mostly of one kind
+// (interior, run of 0 or run of L-1), so it rarely runs every branch of
+// the encoder; each lane reads its block's 128 bytes as 16-byte loads.
 __global__ __launch_bounds__(256) void k_dense_encode(const uint16_t* __restrict__ lut,
                                                       int64_t rows, int32_t detectors,
                                                       int32_t levels, uint64_t* planes,
@@ -55,8 +71,10 @@ __global__ __launch_bounds__(256) void k_dense_encode(const uint16_t* __restrict
     const int NB = (levels + 63) >> 6;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= rows * NB) return;
-    const int64_t row = t / NB;
-    const int blk = (int)(t - row * NB);
+    const int64_t bands = rows / detectors;
+    const int64_t per_block = bands * detectors;  // threads per block index
+    const int blk = (int)(t / per_block);
+    const int64_t row = t - (int64_t)blk * per_block;
     const int64_t b = row / detectors;
     const int64_t d = row - b * detectors;
     const size_t o = ((size_t)b * NB + (size_t)blk) * (size_t)detectors + (size_t)d;
@@ -136,6 +154,9 @@ hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
                 hipFuncAttributes attr;
                 hipError_t e = hipFuncGetAttributes(&attr, (const void*)t.k[v][u][m]);
                 if (e != hipSuccess) return e;
+                // The dense decode addresses LDS from byte 0, which is where
+                // the dynamic LDS starts only with no static LDS.
+                if (m % kModes == kDense && attr.sharedSizeBytes != 0) return hipErrorInvalidImage;
                 worst_static = attr.sharedSizeBytes > worst_static ? attr.sharedSizeBytes
                                                                    : worst_static;
             }

@@ -198,7 +198,7 @@ bool tuned_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels,
         chunks = it->chunks;
     }
     found.chunk_lines = (int32_t)std::max<int64_t>(1, (lines + chunks - 1) / chunks);
-    ApplyParams p;
+    ApplyParams p{};
     size_t lds = 0;
     if (check_plan(found, lines, detectors, bands, levels, vmax, di, &p, &lds) != RC_OK)
         return false;
@@ -299,6 +299,7 @@ std::vector<rc_plan> candidates(int64_t lines, int32_t detectors, int32_t bands,
                         for (int nt = 0; nt < 3; ++nt)
                             for (int k : ks) {
                                 if (vec == 8 && unroll != 4) continue;
+                                if (path == RC_PATH_DENSE && threads > kDenseMaxThreads) continue;
                                 add(path, W, vec, threads, unroll, nt, k);
                             }
     }

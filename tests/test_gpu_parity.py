@@ -185,7 +185,7 @@ def test_uneven_strips(o, shape):
                rc.RC_PATH_DENSE: (L + 63) // 64 * W * 10, rc.RC_PATH_L2: 0}[path]
         if lds > 160 * 1024 or W > 1024 or W // vec > threads:
             continue
-        if path == rc.RC_PATH_DENSE and L > 8192:
+        if path == rc.RC_PATH_DENSE and (L > 8192 or threads > 512):
             continue
         if vec == 8 and unroll != 4:
             continue
@@ -260,12 +260,13 @@ DENSE_SHAPES = [(2, 301, 1000, 4096), (1, 77, 333, 1000), (3, 40, 64, 64), (1, 6
 
 
 @pytest.mark.parametrize("shape", DENSE_SHAPES, ids=lambda s: "x".join(map(str, s)))
-@pytest.mark.parametrize("rows", ["calibration", "clamped", "unpackable"])
+@pytest.mark.parametrize("rows", ["calibration", "clamped", "unpackable", "steep"])
 def test_dense_path(o, shape, rows):
-    """Dense LDS tiles (1 bit per step, per-block slope, saturated runs
-    extrapolated): exact for calibration-like rows, for rows that saturate
-    at both ends inside a block, and through the global-gather fallback for
-    rows that do not fit (decreasing, steep, or steps of 0 and 2 in a block)."""
+    """Dense LDS tiles (1 bit per step, per-block slope 0 or 1, saturated
+    runs extrapolated): exact for calibration-like rows, for rows that
+    saturate at both ends inside a block, and through the global-gather
+    fallback for rows that do not fit (decreasing, steps of 5, slopes
+    growing past 2, and every row with gains of 2 to 3: steps of 2 and 3)."""
     B, N, D, L = shape
     coeffs, dn = pins.tiny_case(L + N + D, B, N, D, L)
     rng = np.random.default_rng(L + D + N)
@@ -278,6 +279,9 @@ def test_dense_path(o, shape, rows):
         # transitions anywhere inside a 64-level block.
         coeffs[..., 0] = rng.uniform(-L / 4, L / 4, size=(B, D))
         coeffs[..., 1] = rng.uniform(0.6, 1.6, size=(B, D))
+    if rows == "steep":
+        coeffs[..., 1] = rng.uniform(2.0, 3.0, size=(B, D))
+        coeffs[..., 2] = 0.0
     if rows == "unpackable":
         coeffs[0, D // 2] = [L - 1, -1.0, 0, 0]      # decreasing
         coeffs[-1, 0] = [0, 5.0, 0, 0]               # steps of 5
@@ -287,8 +291,8 @@ def test_dense_path(o, shape, rows):
     dn_t = to_dev_u16(dn)
     n = 0
     for strip, vec, threads, unroll, chunk, nt, strips in (
-            (256, 8, 256, 4, N, 0, 0), (64, 2, 512, 8, 7, 2, 0), (16, 1, 1024, 16, 3, 4, 0),
-            (128, 4, 256, 4, 1, 0, 0), (256, 4, 256, 8, N, 0, 3), (128, 2, 1024, 8, 11, 5, 2),
+            (256, 8, 256, 4, N, 0, 0), (64, 2, 512, 8, 7, 2, 0), (16, 1, 512, 16, 3, 4, 0),
+            (128, 4, 256, 4, 1, 0, 0), (256, 4, 256, 8, N, 0, 3), (128, 2, 512, 8, 11, 5, 2),
             (256, 1, 256, 8, N, 0, 0)):
         if D % vec or -(-L // 64) * strip * 10 > 160 * 1024 or strip // vec > threads:
             continue
@@ -311,6 +315,17 @@ def test_dense_rejects_long_rows():
     lut = torch.zeros((1, 64, 8200), dtype=torch.int16, device=dev())
     plan = rc.Plan(path=rc.RC_PATH_DENSE, strip=16, vec=2, threads=256, unroll=4, chunk_lines=4,
                    xcd_remap=1, nontemporal=0)
+    with pytest.raises(rc.RcError) as e:
+        rc.correct(dn, lut, plan=plan)
+    assert e.value.status == rc.RC_EINVAL
+
+
+def test_dense_rejects_1024_threads():
+    """The dense kernels are built for at most 512 threads per workgroup."""
+    dn = torch.zeros((1, 4, 64), dtype=torch.int16, device=dev())
+    lut = torch.zeros((1, 64, 4096), dtype=torch.int16, device=dev())
+    plan = rc.Plan(path=rc.RC_PATH_DENSE, strip=16, vec=2, threads=1024, unroll=4,
+                   chunk_lines=4, xcd_remap=1, nontemporal=0)
     with pytest.raises(rc.RcError) as e:
         rc.correct(dn, lut, plan=plan)
     assert e.value.status == rc.RC_EINVAL

@@ -58,7 +58,7 @@ def test_ws_matches_oracle(o, shape, rows):
     if L >= 2048:
         for strip, vec, threads, unroll, chunk, strips in ((256, 4, 512, 8, N, 0),
                                                            (128, 8, 256, 4, 17, 0),
-                                                           (64, 2, 1024, 16, 5, 0),
+                                                           (64, 2, 512, 16, 5, 0),
                                                            (256, 4, 256, 8, 33, 3)):
             if D % vec or -(-L // 64) * strip * 10 > 160 * 1024:
                 continue
