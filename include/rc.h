@@ -390,22 +390,51 @@ typedef struct {
     int32_t graph;        /* 1 if runs replay a captured hipGraph */
     int64_t pixels;
     int64_t lut_entries;
+    int32_t tuned;        /* requests whose tile shape came from a batch entry of the plan
+                             cache (rc_batch_tune); the others use the plain path's plan */
+    int32_t fused;        /* requests whose LUT is written once and never read back: their
+                             tiles evaluate the strip in LDS, or a build kernel writes the
+                             LUT and its dense encoding, which the tiles stage */
+    int64_t lut_gather_entries; /* LUT entries of the other requests (level counts above
+                             8192): written by the build kernel, read back by the gather */
 } rc_batch_stats;
 
 #define RC_BATCH_NO_GRAPH 1 /* flag: launch the two kernels directly on every run */
 
 /*
  * Plans a batch of n requests on the current device: validates every request
- * (RC_EINVAL as for the plain calls, and also if an output of one request
- * overlaps any buffer of another), picks each request's strip shape from the
- * plan cache (or the default plan), builds the tile queue (longest tiles
- * first), allocates the batch's small device tables and captures the LUT
- * build kernel plus the persistent correction kernel into a hipGraph.
+ * (RC_EINVAL as for the plain calls, and also if a buffer written by a
+ * request overlaps any other buffer of any request, except a request's out
+ * equal to its own dn), picks each request's tile shape (its batch entry of
+ * the plan cache, written by rc_batch_tune; else the plain path's plan for
+ * the request fitted to the batch kernel), builds the tile queue (longest
+ * tiles first), allocates the batch's small device tables and captures the
+ * LUT build kernel plus the persistent correction kernel into a hipGraph.
  * Synchronises; not capturable. The request buffers must stay valid until
  * rc_batch_destroy; their contents may change between runs.
+ * flags: 0, or RC_BATCH_NO_GRAPH. This argument is an addition to the
+ * interface the batching step was specified with (requests, count, handle):
+ * it lets callers that capture their own graphs, or cannot, launch directly.
  * Errors: RC_EINVAL, RC_ENOMEM, RC_EHIP.
  */
 rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_batch** out);
+
+/*
+ * Autotunes the batch kernel's tile shape for the shape classes of `reqs`:
+ * requests with pixels are grouped by (levels, ceil(log2 detectors), largest
+ * usable vector width); for each class, candidate shapes (LDS mode, strip
+ * width, pixels per lane) run the class's requests as one batch, launched
+ * directly on `stream` (one warm-up run, then 3 timed with HIP events), and
+ * the fastest goes into the plan cache as that class's batch entry
+ * (rc_tune_save persists it). effort 0 tries the two widest strips and two
+ * vector widths per LDS mode; effort 1 one more of each. The runs write the
+ * requests' lut and out exactly as rc_batch_run would. Validates as
+ * rc_batch_create; synchronises; allocates (each candidate's tables).
+ * *classes (if not NULL) = classes tuned.
+ * Errors: RC_EINVAL, RC_ENOMEM, RC_EHIP.
+ */
+rc_status rc_batch_tune(const rc_request* reqs, int32_t n, int32_t effort, int32_t* classes,
+                        hipStream_t stream);
 
 /* Enqueues one run of the whole batch (LUT build, then correction) on
  * `stream`; no synchronisation, no allocation. Runs on one batch must not
@@ -451,7 +480,9 @@ typedef struct {
  * image into it directly (no device copy of the output, no copy back). The
  * caller owns the buffers and must keep them valid, and not modify dn/coeffs
  * or read out, until rc_server_wait or rc_server_poll reports the job
- * finished.
+ * finished, with any status: a job failed with RC_EHIP is reported only
+ * after the server's streams have drained, so nothing touches its buffers
+ * afterwards.
  */
 typedef struct {
     const double* coeffs;  /* host, [bands][detectors][4] */

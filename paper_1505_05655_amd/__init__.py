@@ -85,7 +85,9 @@ class Request(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_int32), ("tiles", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("pixels", ctypes.c_int64), ("lut_entries", ctypes.c_int64)]
+                ("pixels", ctypes.c_int64), ("lut_entries", ctypes.c_int64),
+                ("tuned", ctypes.c_int32), ("fused", ctypes.c_int32),
+                ("lut_gather_entries", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -161,6 +163,8 @@ _lib.rc_tune_count.argtypes = []
 _lib.rc_tune_count.restype = _i32
 _lib.rc_batch_create.argtypes = [ctypes.POINTER(Request), _i32, _i32, ctypes.POINTER(_vp)]
 _lib.rc_batch_create.restype = ctypes.c_int
+_lib.rc_batch_tune.argtypes = [ctypes.POINTER(Request), _i32, _i32, ctypes.POINTER(_i32), _vp]
+_lib.rc_batch_tune.restype = ctypes.c_int
 _lib.rc_batch_run.argtypes = [_vp, _vp]
 _lib.rc_batch_run.restype = ctypes.c_int
 _lib.rc_batch_info.argtypes = [_vp, ctypes.POINTER(BatchStats)]
@@ -329,6 +333,16 @@ def rc_batch_create(reqs, flags=0):
     return h.value
 
 
+def rc_batch_tune(reqs, effort=0, stream=None):
+    """Tunes the batch tile shape of every class among reqs (sequence of
+    Request) into the plan cache; returns the number of classes tuned."""
+    arr = (Request * len(reqs))(*reqs)
+    n = _i32(0)
+    _check(_lib.rc_batch_tune(arr, len(reqs), effort, ctypes.byref(n), _stream(stream)),
+           "rc_batch_tune")
+    return n.value
+
+
 def rc_batch_run(handle, stream=None):
     _check(_lib.rc_batch_run(handle, _stream(stream)), "rc_batch_run")
 
@@ -343,19 +357,31 @@ def rc_batch_destroy(handle):
     _lib.rc_batch_destroy(handle)
 
 
+def batch_requests(jobs):
+    """Request structs for jobs = [(coeffs, dn, lut, out)] of device tensors
+    (coeffs [B, D, 4] float64, dn/out [B, N, D] 16-bit, lut [B, D, L] 16-bit)."""
+    reqs = []
+    for c, dn, lut, out in jobs:
+        B, N, D = dn.shape
+        assert tuple(c.shape) == (B, D, 4) and tuple(lut.shape[:2]) == (B, D)
+        assert tuple(out.shape) == (B, N, D)
+        reqs.append(Request(_ptr(c), _ptr(dn), _ptr(lut), _ptr(out), N, D, B, lut.shape[2], 0))
+    return reqs
+
+
+def batch_tune(jobs, effort=0, stream=None):
+    """rc_batch_tune over jobs as Batch takes them; returns the classes tuned."""
+    return rc_batch_tune(batch_requests(jobs), effort, stream)
+
+
 class Batch:
     """Owns an rc_batch over device tensors: jobs = [(coeffs, dn, lut, out)], each
     coeffs [B, D, 4] float64, dn/out [B, N, D] 16-bit, lut [B, D, L] 16-bit."""
 
     def __init__(self, jobs, graph=True):
         self.jobs = list(jobs)  # keeps the tensors alive
-        reqs = []
-        for c, dn, lut, out in self.jobs:
-            B, N, D = dn.shape
-            assert tuple(c.shape) == (B, D, 4) and tuple(lut.shape[:2]) == (B, D)
-            assert tuple(out.shape) == (B, N, D)
-            reqs.append(Request(_ptr(c), _ptr(dn), _ptr(lut), _ptr(out), N, D, B, lut.shape[2], 0))
-        self.handle = rc_batch_create(reqs, 0 if graph else RC_BATCH_NO_GRAPH)
+        self.handle = rc_batch_create(batch_requests(self.jobs),
+                                      0 if graph else RC_BATCH_NO_GRAPH)
 
     def run(self, stream=None):
         rc_batch_run(self.handle, stream)

@@ -34,9 +34,14 @@ struct BatchReq {
     int32_t levels;
     int32_t log_strip;
     int32_t vec;
-    int32_t mode;     // kRaw / kGlobal / kPacked
+    int32_t mode;     // kRaw / kGlobal / kPacked / kDense
     int32_t lut_vec;  // LUT rows allow 16-byte loads/stores
-    int32_t fused;    // tiles build their LUT strip in LDS (mode kRaw / kPacked)
+    int32_t fused;    // tiles build their LUT strip in LDS (kRaw / kPacked)
+    int32_t pad;
+    // kDense: the request's dense workspace, [bands][blocks][detectors]
+    // planes and headers, written by k_batch_encode before the tiles run.
+    uint64_t* planes;
+    int16_t* heads;
 };
 
 struct BatchTile {
@@ -69,7 +74,11 @@ BatchQueues single_queue(int32_t n);
 hipError_t prepare_batch_kernel(size_t lds);
 
 // Fills q's strip shape and mode from a plain-path plan, fitted to the
-// persistent kernel's workgroup size and LDS budget.
-void fit_request_plan(const rc_plan& plan, int levels, size_t lds_cap, BatchReq* q);
+// persistent kernel's workgroup size and LDS budget. Dense plans keep the
+// dense mode only if allow_dense (the caller then provides the request's
+// dense workspace and runs k_batch_encode first); otherwise they become
+// packed.
+void fit_request_plan(const rc_plan& plan, int levels, size_t lds_cap, bool allow_dense,
+                      BatchReq* q);
 
 }  // namespace rc

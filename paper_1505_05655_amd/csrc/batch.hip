@@ -1,7 +1,11 @@
 // Batched execution of many uneven correction requests (§I's LUT generation
 // and image correction, run for a whole queue of client scenes at once).
 //
-// Two kernels per run, captured once into a hipGraph and replayed:
+// Up to three kernels per run, captured once into a hipGraph and replayed:
+//  0. k_batch_encode: for the requests with dense tiles (levels <= 8192),
+//     one wave per LUT row evaluates the row from its coefficients, writes
+//     it to the request's LUT and its dense encoding to the batch's
+//     workspace, so the correction tiles only stage and stream.
 //  1. k_lut_build_batch: the LUT entries of the requests that are corrected
 //     from the global LUT (the L2 path, for level counts whose strips do not
 //     fit LDS); a thread finds its request by binary search over the prefix
@@ -36,6 +40,33 @@
 #include "runtime.h"
 
 namespace rc {
+
+// Request r owns LUT rows [rprefix[r], rprefix[r + 1]) (band-major, detector
+// fastest); one wave per row.
+__global__ __launch_bounds__(256) void k_batch_encode(const BatchReq* __restrict__ reqs,
+                                                      const int64_t* __restrict__ rprefix,
+                                                      int32_t nreq, int64_t rows) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t w0 = __builtin_amdgcn_readfirstlane(
+        (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    for (int64_t w = w0; w < rows; w += waves) {
+        int lo = 0, hi = nreq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rprefix[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchReq& q = reqs[lo];
+        const int64_t row = w - rprefix[lo];
+        const int64_t b = row / q.detectors;
+        const int64_t d = row - b * q.detectors;
+        const int NB = (q.levels + 63) >> 6;
+        const double* a = q.coeffs + row * 4;
+        const size_t o = (size_t)b * (size_t)NB * (size_t)q.detectors + (size_t)d;
+        encode_row_wave(a[0], a[1], a[2], a[3], q.levels, q.lut + row * (int64_t)q.levels,
+                        q.lut_vec != 0, q.planes + o, q.heads + o, (size_t)q.detectors);
+    }
+}
 
 __global__ __launch_bounds__(256) void k_lut_build_batch(const BatchReq* __restrict__ reqs,
                                                          const int64_t* __restrict__ prefix,
@@ -96,6 +127,11 @@ __device__ __forceinline__ void batch_tile_vec(const BatchReq& q, const BatchTil
                                                 tl.d0, weff, tl.n0, tl.n1, write_lut, smem,
                                                 q.lut_vec != 0);
         }
+    } else if (q.mode == kDense) {
+        apply_tile<VEC, kBatchUnroll, 0, kDense, false>(q.dn, q.lut, q.out, q.lines, q.detectors,
+                                                        q.levels, q.log_strip, tl.band, tl.d0,
+                                                        weff, tl.n0, tl.n1, smem, q.lut_vec != 0,
+                                                        false, q.planes, q.heads);
     } else {
         apply_tile<VEC, kBatchUnroll, false, kGlobal>(q.dn, q.lut, q.out, q.lines, q.detectors,
                                                       q.levels, q.log_strip, tl.band, tl.d0,
@@ -105,7 +141,10 @@ __device__ __forceinline__ void batch_tile_vec(const BatchReq& q, const BatchTil
 }
 
 // counters[q]: next tile of queue q; counters[kBatchQueues]: workgroups finished.
-__global__ __launch_bounds__(kBatchThreads) void k_apply_batch(const BatchReq* __restrict__ reqs,
+// Two workgroups of kBatchThreads run per CU (8 waves per SIMD): the register
+// budget is set for that occupancy (64 VGPRs).
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_apply_batch(const BatchReq* __restrict__ reqs,
                                                                const BatchTile* __restrict__ tiles,
                                                                BatchQueues queues,
                                                                unsigned int* counters) {
@@ -160,13 +199,22 @@ BatchQueues single_queue(int32_t n) {
 }
 
 hipError_t prepare_batch_kernel(size_t lds) {
+    // The dense tiles address LDS from byte 0: no static LDS may precede the
+    // dynamic buffer.
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, (const void*)k_apply_batch);
+    if (e != hipSuccess) return e;
+    if (attr.sharedSizeBytes != 0) return hipErrorInvalidImage;
     return hipFuncSetAttribute((const void*)k_apply_batch,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-void fit_request_plan(const rc_plan& plan_in, int levels, size_t lds_cap, BatchReq* q) {
+void fit_request_plan(const rc_plan& plan_in, int levels, size_t lds_cap, bool allow_dense,
+                      BatchReq* q) {
     rc_plan p = plan_in;
     if (p.vec > 4) p.vec = 4;  // the persistent kernel takes up to 4 pixels per lane
+    if (p.path == RC_PATH_DENSE && (!allow_dense || levels > kDenseMaxLevels))
+        p.path = RC_PATH_PACKED;
     while (p.path != RC_PATH_L2 && plan_lds_bytes(p.path, p.strip, levels) > lds_cap &&
            p.strip > p.vec)
         p.strip >>= 1;
@@ -177,8 +225,11 @@ void fit_request_plan(const rc_plan& plan_in, int levels, size_t lds_cap, BatchR
     while ((1 << (lw + 1)) <= p.strip) ++lw;
     q->log_strip = lw;
     q->vec = p.vec;
-    q->mode = p.path == RC_PATH_LDS ? kRaw : (p.path == RC_PATH_PACKED ? kPacked : kGlobal);
-    q->fused = q->mode == kGlobal ? 0 : 1;
+    q->mode = p.path == RC_PATH_LDS      ? kRaw
+              : p.path == RC_PATH_PACKED ? kPacked
+              : p.path == RC_PATH_DENSE  ? kDense
+                                         : kGlobal;
+    q->fused = (q->mode == kRaw || q->mode == kPacked) ? 1 : 0;
 }
 
 }  // namespace rc
@@ -191,10 +242,14 @@ struct rc_batch {
     int32_t ntiles = 0;
     int64_t build_items = 0;
     int slots = 0;
+    int cus = 0;
     size_t lds = 0;
     BatchReq* d_reqs = nullptr;
     BatchTile* d_tiles = nullptr;
     int64_t* d_prefix = nullptr;
+    int64_t* d_rprefix = nullptr;   // LUT rows of the dense requests (k_batch_encode)
+    int64_t enc_rows = 0;
+    void* d_ws = nullptr;           // dense workspaces of those requests
     unsigned int* d_counters = nullptr;
     BatchQueues queues{};
     hipStream_t cap = nullptr;
@@ -215,31 +270,77 @@ void release(rc_batch* b) {
     if (b->d_reqs) (void)hipFree(b->d_reqs);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_prefix) (void)hipFree(b->d_prefix);
+    if (b->d_rprefix) (void)hipFree(b->d_rprefix);
+    if (b->d_ws) (void)hipFree(b->d_ws);
     if (b->d_counters) (void)hipFree(b->d_counters);
     delete b;
 }
 
+enum Role { kCoeffs = 0, kLut = 1, kDn = 2, kOut = 3 };
+
 struct Range {
     uintptr_t lo, hi;
     int req;
-    bool written;
+    int role;
+    bool written() const { return role == kLut || role == kOut; }
 };
 
-// A buffer written by one request may not overlap any buffer (read or
-// written) of another request, nor may two written buffers overlap.
+// A buffer written by one request may not overlap any other buffer, read or
+// written, of any request. The one exception is a request corrected in
+// place: its out may be exactly its own dn. (Within a request, fused tiles
+// read the coefficients while other tiles already write the image, so an
+// out that overlaps its own coefficients would race.)
 bool hazards(const std::vector<Range>& rs) {
     for (size_t a = 0; a < rs.size(); ++a) {
-        if (!rs[a].written) continue;
+        if (!rs[a].written()) continue;
         for (size_t b = 0; b < rs.size(); ++b) {
             if (a == b) continue;
-            if (rs[b].req == rs[a].req && !rs[b].written) continue;  // own inputs (in place)
+            if (rs[b].req == rs[a].req && rs[a].role == kOut && rs[b].role == kDn &&
+                rs[a].lo == rs[b].lo && rs[a].hi == rs[b].hi)
+                continue;  // in place
             if (rs[a].lo < rs[b].hi && rs[b].lo < rs[a].hi) return true;
         }
     }
     return false;
 }
 
+// Validates every request and the hazards between them (host only).
+rc_status validate_requests(const rc_request* reqs, int32_t n) {
+    std::vector<Range> ranges;
+    for (int32_t i = 0; i < n; ++i) {
+        const rc_request& r = reqs[i];
+        if (r.lines < 0 || r.detectors < 0 || r.bands < 0 || r.reserved != 0) return RC_EINVAL;
+        if (r.levels < RC_LEVELS_MIN || r.levels > RC_LEVELS_MAX) return RC_EINVAL;
+        int64_t px = 0, rows = 0, lut_n = 0;
+        if (!mul_ok(r.lines, r.detectors, &px) || !mul_ok(px, r.bands, &px) ||
+            !mul_ok((int64_t)r.bands, r.detectors, &rows) || !mul_ok(rows, r.levels, &lut_n) ||
+            px > INT64_MAX / 2 || lut_n > INT64_MAX / 2)
+            return RC_EINVAL;
+        if (rows > 0) {
+            if (!r.coeffs || !r.lut || ((uintptr_t)r.coeffs & 7u) || ((uintptr_t)r.lut & 1u))
+                return RC_EINVAL;
+            ranges.push_back({(uintptr_t)r.lut, (uintptr_t)r.lut + (uintptr_t)lut_n * 2, i, kLut});
+            ranges.push_back({(uintptr_t)r.coeffs, (uintptr_t)r.coeffs + (uintptr_t)rows * 32, i,
+                              kCoeffs});
+        }
+        if (px > 0) {
+            if (!r.dn || !r.out || (((uintptr_t)r.dn | (uintptr_t)r.out) & 1u)) return RC_EINVAL;
+            ranges.push_back({(uintptr_t)r.out, (uintptr_t)r.out + (uintptr_t)px * 2, i, kOut});
+            ranges.push_back({(uintptr_t)r.dn, (uintptr_t)r.dn + (uintptr_t)px * 2, i, kDn});
+        }
+    }
+    return hazards(ranges) ? RC_EINVAL : RC_OK;
+}
+
 hipError_t enqueue(const rc_batch* b, hipStream_t s) {
+    if (b->enc_rows > 0) {
+        const int64_t cap = (int64_t)std::max(1, b->cus) * 16;
+        const int64_t blocks = std::min<int64_t>((b->enc_rows + 3) / 4, cap);
+        hipLaunchKernelGGL(k_batch_encode, dim3((unsigned)blocks), dim3(256), 0, s, b->d_reqs,
+                           b->d_rprefix, b->nreq, b->enc_rows);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (b->build_items > 0) {
         int64_t blocks = (b->build_items + 255) / 256;
         if (blocks > ((int64_t)1 << 20)) blocks = (int64_t)1 << 20;
@@ -257,41 +358,18 @@ hipError_t enqueue(const rc_batch* b, hipStream_t s) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_batch** out) {
+// The batch of n requests; every request takes the tile shape *forced when
+// it is given (the tuner's candidates), else its batch entry of the plan
+// cache, else the plain path's plan fitted to the batch kernel.
+rc_status batch_create(const rc_request* reqs, int32_t n, int32_t flags, const rc_plan* forced,
+                       rc_batch** out) {
     if (!out || n < 0 || (n > 0 && !reqs)) return RC_EINVAL;
     *out = nullptr;
     // Pass 1, host only: validate every request and the hazards between them.
-    std::vector<Range> ranges;
-    for (int32_t i = 0; i < n; ++i) {
-        const rc_request& r = reqs[i];
-        if (r.lines < 0 || r.detectors < 0 || r.bands < 0 || r.reserved != 0) return RC_EINVAL;
-        if (r.levels < RC_LEVELS_MIN || r.levels > RC_LEVELS_MAX) return RC_EINVAL;
-        int64_t px = 0, rows = 0, lut_n = 0;
-        if (!mul_ok(r.lines, r.detectors, &px) || !mul_ok(px, r.bands, &px) ||
-            !mul_ok((int64_t)r.bands, r.detectors, &rows) || !mul_ok(rows, r.levels, &lut_n) ||
-            px > INT64_MAX / 2 || lut_n > INT64_MAX / 2)
-            return RC_EINVAL;
-        if (rows > 0) {
-            if (!r.coeffs || !r.lut || ((uintptr_t)r.coeffs & 7u) || ((uintptr_t)r.lut & 1u))
-                return RC_EINVAL;
-            if (overlaps(r.coeffs, (size_t)rows * 32, r.lut, (size_t)lut_n * 2)) return RC_EINVAL;
-            ranges.push_back({(uintptr_t)r.lut, (uintptr_t)r.lut + (uintptr_t)lut_n * 2, i, true});
-            ranges.push_back({(uintptr_t)r.coeffs, (uintptr_t)r.coeffs + (uintptr_t)rows * 32, i,
-                              false});
-        }
-        if (px > 0) {
-            if (!r.dn || !r.out || (((uintptr_t)r.dn | (uintptr_t)r.out) & 1u)) return RC_EINVAL;
-            if (r.dn != r.out && overlaps(r.dn, (size_t)px * 2, r.out, (size_t)px * 2))
-                return RC_EINVAL;
-            // The LUT is written before the image is read: it may not overlap dn.
-            if (overlaps(r.lut, (size_t)lut_n * 2, r.dn, (size_t)px * 2)) return RC_EINVAL;
-            ranges.push_back({(uintptr_t)r.out, (uintptr_t)r.out + (uintptr_t)px * 2, i, true});
-            ranges.push_back({(uintptr_t)r.dn, (uintptr_t)r.dn + (uintptr_t)px * 2, i, false});
-        }
-    }
-    if (hazards(ranges)) return RC_EINVAL;
+    const rc_status vs = validate_requests(reqs, n);
+    if (vs != RC_OK) return vs;
 
     // Pass 2: per-request plans and the tile queue.
     const DeviceInfo* di = current_device();
@@ -300,7 +378,13 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
     std::vector<BatchReq> hreq;
     std::vector<BatchTile> htile;
     std::vector<int64_t> prefix(1, 0);
-    int64_t total_px = 0, total_lut = 0;
+    std::vector<int64_t> rprefix(1, 0);
+    // Dense workspace of request i: planes at ws_planes[i], headers at
+    // ws_heads[i] (bytes into the batch's workspace), each 256-byte aligned.
+    std::vector<size_t> ws_planes(n, 0), ws_heads(n, 0);
+    size_t ws_total = 0;
+    int64_t total_px = 0, total_lut = 0, gather_lut = 0;
+    int32_t ntuned = 0, nfused = 0;
     for (int32_t i = 0; i < n; ++i) {
         const rc_request& r = reqs[i];
         const int64_t px = r.lines * r.detectors * (int64_t)r.bands;
@@ -321,9 +405,23 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
             const int vmax = px > 0 ? max_vec(r.dn, r.out, r.detectors) : 1;
             const int64_t lines_p = std::max<int64_t>(r.lines, 1);
             rc_plan p;
-            if (!tuned_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p))
+            if (forced) {
+                p = *forced;
+            } else if (tuned_batch_shape(r.detectors, r.levels, vmax, *di, &p)) {
+                ++ntuned;
+            } else if (!tuned_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p)) {
                 pow2_plan(lines_p, r.detectors, r.bands, r.levels, vmax, *di, &p);
-            fit_request_plan(p, r.levels, lds_cap, &q);
+            }
+            fit_request_plan(p, r.levels, lds_cap, true, &q);
+            if (q.mode == kGlobal) gather_lut += lut_n;  // read back by the gather
+            else ++nfused;                                // never read back
+            if (q.mode == kDense) {
+                const size_t nbl = (size_t)rows * (size_t)((r.levels + 63) / 64);
+                ws_planes[i] = ws_total;
+                ws_total += (nbl * 8 + 255) & ~(size_t)255;
+                ws_heads[i] = ws_total;
+                ws_total += (nbl * 2 + 255) & ~(size_t)255;
+            }
             const int lw = q.log_strip;
             // One tile per (band, strip) and line chunk; strips of up to 8192
             // lines are not split (re-staging the LUT strip per chunk would
@@ -336,7 +434,8 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
             for (int32_t b = 0; b < r.bands; ++b)
                 for (int32_t d0 = 0; d0 < r.detectors; d0 += W) {
                     // A fused request with no lines still gets one tile per
-                    // strip, which only builds the LUT.
+                    // strip, which only builds the LUT (the other modes'
+                    // LUTs come from the build kernels).
                     const int64_t nend = (r.lines == 0 && q.fused) ? 1 : r.lines;
                     for (int64_t n0 = 0; n0 < nend; n0 += ch) {
                         BatchTile tl;
@@ -351,8 +450,10 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
                 }
         }
         hreq.push_back(q);
-        const int64_t items = q.fused ? 0 : rows * (int64_t)((r.levels + 7) / 8);
+        const int64_t items =
+            (rows > 0 && q.mode == kGlobal) ? rows * (int64_t)((r.levels + 7) / 8) : 0;
         prefix.push_back(prefix.back() + items);
+        rprefix.push_back(rprefix.back() + ((rows > 0 && q.mode == kDense) ? rows : 0));
         total_px += px;
         total_lut += lut_n;
     }
@@ -426,6 +527,8 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
     bt->ntiles = (int32_t)htile.size();
     bt->queues = queues;
     bt->build_items = prefix.back();
+    bt->enc_rows = rprefix.back();
+    bt->cus = di->cus;
     bt->lds = lds_cap;
     bt->use_graph = !(flags & RC_BATCH_NO_GRAPH);
     bt->slots = std::max(1, di->cus) *
@@ -438,6 +541,16 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
     if (n > 0) {
         if ((e = hipMalloc(&bt->d_reqs, sizeof(BatchReq) * n)) != hipSuccess) return fail(e);
         if ((e = hipMalloc(&bt->d_prefix, sizeof(int64_t) * (n + 1))) != hipSuccess) return fail(e);
+        if ((e = hipMalloc(&bt->d_rprefix, sizeof(int64_t) * (n + 1))) != hipSuccess)
+            return fail(e);
+    }
+    if (ws_total > 0) {
+        if ((e = hipMalloc(&bt->d_ws, ws_total)) != hipSuccess) return fail(e);
+        for (int32_t i = 0; i < n; ++i) {
+            if (hreq[i].mode != kDense || !ws_heads[i]) continue;
+            hreq[i].planes = (uint64_t*)((char*)bt->d_ws + ws_planes[i]);
+            hreq[i].heads = (int16_t*)((char*)bt->d_ws + ws_heads[i]);
+        }
     }
     if (!htile.empty() &&
         (e = hipMalloc(&bt->d_tiles, sizeof(BatchTile) * htile.size())) != hipSuccess)
@@ -451,6 +564,9 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
                                 hipMemcpyHostToDevice, bt->cap)) != hipSuccess)
             return fail(e);
         if ((e = hipMemcpyAsync(bt->d_prefix, prefix.data(), sizeof(int64_t) * (n + 1),
+                                hipMemcpyHostToDevice, bt->cap)) != hipSuccess)
+            return fail(e);
+        if ((e = hipMemcpyAsync(bt->d_rprefix, rprefix.data(), sizeof(int64_t) * (n + 1),
                                 hipMemcpyHostToDevice, bt->cap)) != hipSuccess)
             return fail(e);
     }
@@ -480,8 +596,150 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
     st.pixels = total_px;
     st.lut_entries = total_lut;
     st.graph = bt->use_graph ? 1 : 0;
+    st.tuned = ntuned;
+    st.fused = nfused;
+    st.lut_gather_entries = gather_lut;
     *out = bt;
     return RC_OK;
+}
+
+// Candidate tile shapes of the batch kernel for requests with `levels`
+// levels, at most `dmax` detectors and vector width up to vmax: the LDS
+// paths at the widest strip that fits the batch's tile budget and narrower
+// ones, the L2 path at two widths, each with the widest and the next
+// pixels per lane.
+std::vector<rc_plan> batch_candidates(int32_t levels, int32_t dmax, int vmax, size_t lds_cap,
+                                      int effort) {
+    std::vector<rc_plan> out;
+    int wcap = 8;
+    while (wcap < dmax && wcap < 1024) wcap <<= 1;
+    std::vector<int> vecs;
+    for (int v = std::min(vmax, 4); v >= 1 && (int)vecs.size() < (effort ? 3 : 2); v >>= 1)
+        vecs.push_back(v);
+    auto add = [&](int path, int W, int vec) {
+        if (W < vec || W > wcap || W / vec > kBatchThreads) return;
+        rc_plan p;
+        std::memset(&p, 0, sizeof p);
+        p.path = path;
+        p.strip = W;
+        p.vec = vec;
+        p.threads = kBatchThreads;
+        p.unroll = kBatchUnroll;
+        p.chunk_lines = 1;
+        p.xcd_remap = 1;
+        out.push_back(p);
+    };
+    for (int path : {RC_PATH_DENSE, RC_PATH_PACKED, RC_PATH_LDS}) {
+        if (path == RC_PATH_DENSE && levels > kDenseMaxLevels) continue;
+        int w0 = 0;
+        for (int W = 1024; W >= 8; W >>= 1)
+            if (plan_lds_bytes(path, W, levels) <= lds_cap) {
+                w0 = std::min(W, wcap);
+                break;
+            }
+        if (!w0) continue;
+        for (int k = 0; k < (effort ? 3 : 2); ++k)
+            for (int v : vecs) add(path, w0 >> k, v);
+    }
+    for (int W : {64, 128})
+        for (int v : vecs) add(RC_PATH_L2, W, v);
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_batch** out) {
+    return batch_create(reqs, n, flags, nullptr, out);
+}
+
+rc_status rc_batch_tune(const rc_request* reqs, int32_t n, int32_t effort, int32_t* classes,
+                        hipStream_t stream) {
+    if (classes) *classes = 0;
+    if (n < 0 || (n > 0 && !reqs)) return RC_EINVAL;
+    const rc_status vs = validate_requests(reqs, n);
+    if (vs != RC_OK) return vs;
+    const DeviceInfo* di = current_device();
+    if (!di) return RC_EHIP;
+    const size_t lds_cap = std::min(kBatchLds, di->lds);
+    // Shape classes: (levels, ceil(log2 detectors), vector width), over the
+    // requests that have pixels.
+    struct Cls {
+        int32_t levels;
+        int dclass;
+        int vmax;
+        int32_t dmax;
+        std::vector<rc_request> reqs;
+    };
+    std::vector<Cls> cls;
+    for (int32_t i = 0; i < n; ++i) {
+        const rc_request& r = reqs[i];
+        if (r.lines <= 0 || r.detectors <= 0 || r.bands <= 0) continue;
+        const int vmax = max_vec(r.dn, r.out, r.detectors);
+        int dc = 0;
+        while (((int64_t)1 << dc) < r.detectors) ++dc;
+        auto it = std::find_if(cls.begin(), cls.end(), [&](const Cls& c) {
+            return c.levels == r.levels && c.dclass == dc && c.vmax == vmax;
+        });
+        if (it == cls.end()) {
+            cls.push_back(Cls{r.levels, dc, vmax, 0, {}});
+            it = cls.end() - 1;
+        }
+        it->dmax = std::max(it->dmax, r.detectors);
+        it->reqs.push_back(r);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    rc_status st = e == hipSuccess ? RC_OK : hip_fail(e);
+    const int reps = 3;
+    int32_t done = 0;
+    for (const Cls& c : cls) {
+        if (st != RC_OK) break;
+        float best = 1e30f;
+        rc_plan best_p{};
+        for (const rc_plan& cand :
+             batch_candidates(c.levels, c.dmax, c.vmax, lds_cap, effort)) {
+            rc_batch* b = nullptr;
+            const rc_status cs = batch_create(c.reqs.data(), (int32_t)c.reqs.size(),
+                                              RC_BATCH_NO_GRAPH, &cand, &b);
+            if (cs == RC_EINVAL) continue;  // not runnable for this class
+            if (cs != RC_OK) {
+                st = cs;
+                break;
+            }
+            float ms = 0.f;
+            if ((e = enqueue(b, stream)) == hipSuccess &&  // warm-up run
+                (e = hipEventRecord(e0, stream)) == hipSuccess) {
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = enqueue(b, stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            }
+            // The runs must be over before the batch's tables are freed.
+            const hipError_t se = hipStreamSynchronize(stream);
+            if (e == hipSuccess) e = se;
+            release(b);
+            if (e != hipSuccess) {
+                st = hip_fail(e);
+                break;
+            }
+            ms /= reps;
+            if (ms < best) {
+                best = ms;
+                best_p = cand;
+            }
+        }
+        if (st == RC_OK && best < 1e30f) {
+            store_batch_shape(c.dmax, c.levels, c.vmax, *di, best_p, best * 1000.0);
+            ++done;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (classes) *classes = done;
+    return st;
 }
 
 rc_status rc_batch_run(rc_batch* b, hipStream_t stream) {

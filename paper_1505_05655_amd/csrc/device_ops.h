@@ -272,22 +272,21 @@ __host__ __device__ constexpr size_t packed_lds_bytes(int W, int L) {
 // 160 KiB. Encodable blocks: non-decreasing, with the steps between
 // unsaturated entries within {s, s+1}, s <= 1 (calibration LUTs: gains
 // below 2); other rows make the tile gather from the global LUT.
-// Layout: headers [NB][W] (int16) from byte 0, planes [NB][W] (64-bit) from
-// byte kDenseHeads = 32 KiB (a tile's NB x W blocks never exceed 16384 in
-// 160 KiB), detector j of the strip at position p = (j % VEC) * (W / VEC) +
-// j / VEC, as the packed strip. Requires L <= kDenseMaxLevels = 8192
-// (header range).
-constexpr int kDenseHeads = 32768;
+// Layout: planes [NB][W] (64-bit) from byte 0, then headers [NB][W] (int16)
+// from byte NB * W * 8; detector j of the strip at position p = (j % VEC) *
+// (W / VEC) + j / VEC, as the packed strip. A lane keeps 8p and its header
+// base NB*W*8 + 2p, so each of the two addresses of a level is one shift-add
+// of the block index. Requires L <= kDenseMaxLevels = 8192 (header range).
 constexpr int16_t kDenseBad = -32768;
 
 __host__ __device__ constexpr size_t dense_lds_bytes(int W, int L) {
-    return (size_t)kDenseHeads + (size_t)((L + 63) / 64) * (size_t)W * 8;
+    return (size_t)((L + 63) / 64) * (size_t)W * 10;
 }
 
 // LDS addressed from byte 0: the correction kernels have no static LDS, so
-// their dynamic LDS starts at 0 (prepare_apply_kernels checks it on the host
-// and refuses the dense mode otherwise); with the base a known constant no
-// address needs an add for it.
+// their dynamic LDS starts at 0 (prepare_apply_kernels and
+// prepare_batch_kernel check it on the host and refuse otherwise); with the
+// base a known constant no address needs an add for it.
 typedef __attribute__((address_space(3))) const uint64_t lds_u64;
 typedef __attribute__((address_space(3))) const int16_t lds_i16;
 
@@ -307,12 +306,14 @@ __device__ __forceinline__ int bcnt_acc(uint32_t x, int acc) {
     return r;
 }
 
-// p8 = 8 * p (the lane's position, in bytes of the plane array).
-__device__ __forceinline__ uint32_t g_dense(uint32_t dnv, uint32_t top, int logW, uint32_t p8) {
+// p8 = 8p, h2 = NB*W*8 + 2p (the lane's position p in the plane and header
+// arrays, in bytes from the start of LDS).
+__device__ __forceinline__ uint32_t g_dense(uint32_t dnv, uint32_t top, int logW, uint32_t p8,
+                                            uint32_t h2) {
     const uint32_t v = dnv < top ? dnv : top;
-    const uint32_t a8 = ((v >> 6) << (logW + 3)) + p8;  // 8 x block index
-    const uint64_t z = *(lds_u64*)(uintptr_t)(kDenseHeads + a8);
-    const int h = *(lds_i16*)(uintptr_t)(a8 >> 2);
+    const uint32_t blk = v >> 6;
+    const uint64_t z = *(lds_u64*)(uintptr_t)((blk << (logW + 3)) + p8);
+    const int h = *(lds_i16*)(uintptr_t)((blk << (logW + 1)) + h2);
     const uint64_t sh = z << (v & 63u);
     int u = (int)(v << ((uint32_t)z & 1u)) + h;
     u = bcnt_acc((uint32_t)(sh >> 32), u);
@@ -467,7 +468,10 @@ __device__ __forceinline__ int packed_any(int flag, u32x2* planes) {
 // W / VEC <= blockDim.x, and the LDS size of the mode for W detectors. dn and
 // out may be the same buffer (in place): every pixel is read and then written
 // by the same lane, so they are deliberately not __restrict__.
-template <int VEC, int UNROLL, int NT, int MODE>
+// LANE_ENCODE: the dense mode may encode its strip from the global LUT
+// (false: the caller always passes a pre-encoded strip, and the encoder is
+// not compiled in).
+template <int VEC, int UNROLL, int NT, int MODE, bool LANE_ENCODE = true>
 __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* __restrict__ lut,
                                            uint16_t* out, int64_t N, int D, int L, int logW,
                                            int b, int d0, int weff, int64_t n0, int64_t n1,
@@ -570,8 +574,9 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
         }
     } else if constexpr (MODE == kDense) {
         const int NB = (L + 63) >> 6;
-        int16_t* heads = (int16_t*)smem;
-        uint64_t* planes = (uint64_t*)((unsigned char*)smem + kDenseHeads);
+        const uint32_t hb = (uint32_t)NB << (logW + 3);  // header array, bytes from LDS start
+        uint64_t* planes = (uint64_t*)smem;
+        int16_t* heads = (int16_t*)((unsigned char*)smem + hb);
         int bad = 0;
         if (pre_planes) {
             // Stage the blocks k_dense_encode wrote ([band][block][detector]):
@@ -592,8 +597,8 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
         // Stage: one lane encodes one block (detector jj, 64 levels); a wave
         // covers 64 consecutive LDS positions of one block index, so its
         // plane and header writes are consecutive words.
-        const int units = pre_planes ? 0 : NB << logW;
-        for (int u = tid; u < units; u += nt) {
+        const int units = (!LANE_ENCODE || pre_planes) ? 0 : NB << logW;
+        for (int u = tid; LANE_ENCODE && u < units; u += nt) {
             const int blk = u >> logW;
             const int p = u & (W - 1);
             const int jj = ((p & ((1 << logq) - 1)) << LOGVEC) + (p >> logq);
@@ -629,7 +634,8 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
             if (!bad) {
                 stream_lines<VEC, UNROLL, NT>(
                     rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
-                        return g_dense(d, top, logW, (uint32_t)((k << logq) + lane) * 8u);
+                        const uint32_t p = (uint32_t)((k << logq) + lane);
+                        return g_dense(d, top, logW, p * 8u, hb + p * 2u);
                     }, pass_adv);
             } else {
                 const uint16_t* lrow = strip_lut + (size_t)j * Lz;
@@ -788,6 +794,124 @@ __device__ __forceinline__ void store_lut8(uint16_t* dst, const uint32_t* e, int
         __builtin_nontemporal_store(q, (u32x4*)dst);
     } else {
         for (int k = 0; k < n; ++k) dst[k] = (uint16_t)e[k];
+    }
+}
+
+// One LUT row evaluated from its calibration coefficients by one wave,
+// written to `dst` (L entries) and encoded in the dense form: block blk's
+// plane and header go to planes[blk * stride] and heads[blk * stride] (the
+// [band][block][detector] layout of a dense workspace); a block the form
+// cannot hold gets the header kDenseBad. 8 blocks per pass: lane 8g + q
+// computes levels 64 (8 r + g) + 8q .. + 7, so a pass stores 1 KiB of the
+// row contiguously; the 8 lanes of a block decide its form (the cases of
+// dense_encode) with xor-shuffles inside their group and OR their step bits
+// together. Every lane of the wave must call it.
+__device__ __forceinline__ void encode_row_wave(double a0, double a1, double a2, double a3, int L,
+                                                uint16_t* dst, bool lut_vec, uint64_t* planes,
+                                                int16_t* heads, size_t stride) {
+    const int NB = (L + 63) >> 6;
+    const int top = L - 1;
+    const double lim = (double)L;
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = lane >> 3, q = lane & 7;
+    const int rounds = (NB + 7) >> 3;
+    auto gmin = [](int x) {
+        x = min(x, __shfl_xor(x, 1, 64));
+        x = min(x, __shfl_xor(x, 2, 64));
+        return min(x, __shfl_xor(x, 4, 64));
+    };
+    auto gmax = [](int x) {
+        x = max(x, __shfl_xor(x, 1, 64));
+        x = max(x, __shfl_xor(x, 2, 64));
+        return max(x, __shfl_xor(x, 4, 64));
+    };
+    constexpr int kBig = 1 << 20;
+    for (int r = 0; r < rounds; ++r) {
+        const int blk = (r << 3) + g;
+        const int vb = blk << 6;
+        const int cnt = min(64, L - vb);  // entries of the block (<= 0 past the row)
+        const int v0 = vb + (q << 3);
+        const int n = max(0, min(8, L - v0));
+        int e[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) e[k] = k < n ? (int)lut_entry(a0, a1, a2, a3, v0 + k, lim) : 0;
+        if (n > 0) {
+            uint32_t w[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) w[k] = (uint32_t)e[k];
+            store_lut8(dst + v0, w, n, lut_vec);
+        }
+        // Steps t = 8q + k (entry t+1 minus entry t) inside the block.
+        const int nxt = __shfl_down(e[0], 1, 64);
+        int mn = kBig, mx = -kBig, smin = kBig, smax = -kBig, first = 64;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int t = (q << 3) + k;
+            const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
+            if (t + 1 < cnt) {
+                mn = min(mn, eb - ea);
+                mx = max(mx, eb - ea);
+                if (eb != 0 && ea != top) {
+                    smin = min(smin, eb - ea);
+                    smax = max(smax, eb - ea);
+                }
+                if (ea == 0 && eb != 0) first = min(first, t + 1);
+            }
+        }
+        mn = gmin(mn);
+        mx = gmax(mx);
+        smin = gmin(smin);
+        smax = gmax(smax);
+        first = min(gmin(first), max(cnt, 0));
+        const int e0 = __shfl(e[0], lane & ~7, 64);
+        int last = -1;  // entry cnt - 1, held by one lane of the group
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((q << 3) + k == cnt - 1) last = e[k];
+        last = gmax(last);
+        bool ok = true;
+        int s = 0, u0 = e0, kind = 0;  // 0 constant, 1 unsaturated, 2 transition
+        if (cnt > 1 && mn < 0) {
+            ok = false;
+        } else if (cnt <= 1 || e0 == top || last == 0) {
+            kind = 0;
+        } else if (e0 != 0 && last != top) {
+            kind = 1;
+            s = max(0, mx - 1);
+            ok = s <= 1 && mn >= s;
+        } else {
+            kind = 2;
+            s = max(0, smax - 1);
+            ok = s <= 1 && smin >= s;
+            if (e0 == 0) u0 = -(s + 1) * (first - 1);
+        }
+        uint32_t lo8 = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
+            int bit = 0;
+            if ((q << 3) + k + 1 < cnt) {
+                if (kind == 1) bit = eb - ea - s;
+                if (kind == 2) bit = (eb != 0 && ea != top) ? eb - ea - s : 1;
+            }
+            lo8 |= (uint32_t)(bit & 1) << k;
+        }
+        // Bit t+1 of the block word = b_t: this lane's bits start at 8q+1.
+        const uint64_t mine = (uint64_t)lo8 << ((q << 3) + 1);
+        uint32_t blo = (uint32_t)mine, bhi = (uint32_t)(mine >> 32);
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1) {
+            blo |= (uint32_t)__shfl_xor((int)blo, m, 64);
+            bhi |= (uint32_t)__shfl_xor((int)bhi, m, 64);
+        }
+        const uint64_t bits = ((uint64_t)bhi << 32) | blo;
+        const uint64_t z = (~(__builtin_bitreverse64(bits) << 1) & ~(uint64_t)1) | (uint64_t)s;
+        const int H = u0 + __builtin_popcountll(bits) - 63 - 64 * (s + 1) * blk - s;
+        if (H <= (int)kDenseBad || H > 32767) ok = false;
+        if (q == 0 && blk < NB) {
+            planes[(size_t)blk * stride] = ok ? z : 0;
+            heads[(size_t)blk * stride] = ok ? (int16_t)H : kDenseBad;
+        }
     }
 }
 

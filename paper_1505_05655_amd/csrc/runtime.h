@@ -79,6 +79,15 @@ int plan_slots(const rc_plan& plan, size_t lds_bytes, const DeviceInfo& di);
 bool tuned_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, int vmax,
                 const DeviceInfo& di, rc_plan* plan);
 
+// Batch entries of the plan cache: the persistent batch kernel's tile shape
+// (path, strip, vec of *plan) for requests of a class (levels,
+// ceil(log2 detectors), largest usable vector width), as rc_batch_tune
+// stores it.
+bool tuned_batch_shape(int32_t detectors, int32_t levels, int vmax, const DeviceInfo& di,
+                       rc_plan* plan);
+void store_batch_shape(int32_t detectors, int32_t levels, int vmax, const DeviceInfo& di,
+                       const rc_plan& plan, double us);
+
 // Validation helpers.
 bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 bool mul_ok(int64_t a, int64_t b, int64_t* r);

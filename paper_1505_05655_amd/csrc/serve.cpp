@@ -241,6 +241,14 @@ rc_status validate_job(const rc_host_job& j) {
 // Marks the server failed: every unfinished job completes with RC_EHIP.
 void fail_all(rc_server* s, hipError_t e) {
     s->failed = (int)e;
+    // Copies and quanta already enqueued for the active jobs may still read
+    // or write their host buffers (pinned staging, or out directly): all
+    // three streams drain before any job is reported finished, so that a
+    // caller may free its buffers as soon as wait/poll returns. After a
+    // device fault these waits return at once, with the error.
+    (void)hipStreamSynchronize(s->s_in);
+    (void)hipStreamSynchronize(s->s_comp);
+    (void)hipStreamSynchronize(s->s_out);
     const double t = now_s();
     for (auto& j : s->active) {
         j->status = RC_EHIP;
@@ -281,7 +289,7 @@ hipError_t admit(rc_server* s, const std::shared_ptr<Job>& jp) {
         rc_plan p;
         if (!tuned_plan(lines_p, h.detectors, h.bands, h.levels, vmax, *s->di, &p))
             pow2_plan(lines_p, h.detectors, h.bands, h.levels, vmax, *s->di, &p);
-        fit_request_plan(p, h.levels, s->lds, &q);
+        fit_request_plan(p, h.levels, s->lds, false, &q);
     }
     // Pieces: per band, runs of lines of about piece_pixels pixels.
     const int64_t cap = std::min<int64_t>(

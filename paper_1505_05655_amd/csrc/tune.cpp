@@ -8,6 +8,9 @@
 // stored as a chunk count, so one entry serves every line count of its
 // class. The cache persists as one JSON object per line; rc_correct consults
 // it (host only, no synchronisation) and falls back to the default plan.
+// Batch entries ("kind":1, written by rc_batch_tune in batch.hip) hold the
+// persistent batch kernel's tile shape for a class (levels, ceil(log2
+// detectors), largest usable vector width); lines and bands are 0 there.
 #include <dlfcn.h>
 #include <hip/hip_runtime_api.h>
 
@@ -39,6 +42,7 @@ struct Entry {
     rc_plan plan{};
     int chunks = 1;  // line chunks per strip (chunk_lines = ceil(lines / chunks))
     double us = 0.0;
+    int kind = 0;    // 0: plain-path plan, 1: batch tile shape
 };
 
 std::mutex g_mu;
@@ -80,12 +84,16 @@ bool get_num(const std::string& line, const char* key, double* out) {
 }
 
 bool get_str(const std::string& line, const char* key, std::string* out) {
-    const std::string k = std::string("\"") + key + "\":\"";
+    const std::string k = std::string("\"") + key + "\":";
     const size_t at = line.find(k);
     if (at == std::string::npos) return false;
-    const size_t end = line.find('"', at + k.size());
+    size_t begin = at + k.size();
+    while (begin < line.size() && (line[begin] == ' ' || line[begin] == '\t')) ++begin;
+    if (begin >= line.size() || line[begin] != '"') return false;
+    ++begin;
+    const size_t end = line.find('"', begin);
     if (end == std::string::npos) return false;
-    *out = line.substr(at + k.size(), end - at - k.size());
+    *out = line.substr(begin, end - begin);
     return true;
 }
 
@@ -115,7 +123,8 @@ bool parse_entry(const std::string& line, Entry* e) {
     double st = 0.0;
     e->plan.strips = get_num(line, "strips", &st) ? (int32_t)st : 0;
     e->plan.lane_map = get_num(line, "lane_map", &st) ? (int32_t)st : 0;
-    if (e->plan.strips < 0) return false;
+    e->kind = get_num(line, "kind", &st) ? (int)st : 0;
+    if (e->plan.strips < 0 || e->kind < 0 || e->kind > 1) return false;
     return true;
 }
 
@@ -148,11 +157,12 @@ int save_locked(const std::string& path) {
                      "{\"arch\":\"%s\",\"cus\":%d,\"levels\":%d,\"dclass\":%d,\"nclass\":%d,"
                      "\"bands\":%d,\"vmax\":%d,\"path\":%d,\"strip\":%d,\"vec\":%d,"
                      "\"threads\":%d,\"unroll\":%d,\"chunks\":%d,\"xcd_remap\":%d,"
-                     "\"nontemporal\":%d,\"strips\":%d,\"lane_map\":%d,\"us\":%.3f}\n",
+                     "\"nontemporal\":%d,\"strips\":%d,\"lane_map\":%d,\"kind\":%d,"
+                     "\"us\":%.3f}\n",
                      e.arch.c_str(), e.cus, e.levels, e.dclass, e.nclass, e.bands, e.vmax,
                      e.plan.path, e.plan.strip, e.plan.vec, e.plan.threads, e.plan.unroll,
                      e.chunks, e.plan.xcd_remap, e.plan.nontemporal, e.plan.strips,
-                     e.plan.lane_map, e.us);
+                     e.plan.lane_map, e.kind, e.us);
     }
     const bool ok = std::fclose(f) == 0;
     if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) return -1;
@@ -173,8 +183,14 @@ Entry key_of(int64_t lines, int32_t detectors, int32_t bands, int32_t levels, in
 }
 
 bool same_class(const Entry& a, const Entry& b) {
-    return a.arch == b.arch && a.cus == b.cus && a.levels == b.levels && a.dclass == b.dclass &&
-           a.nclass == b.nclass && a.bands == b.bands && a.vmax == b.vmax;
+    return a.kind == b.kind && a.arch == b.arch && a.cus == b.cus && a.levels == b.levels &&
+           a.dclass == b.dclass && a.nclass == b.nclass && a.bands == b.bands && a.vmax == b.vmax;
+}
+
+Entry batch_key(int32_t detectors, int32_t levels, int vmax, const DeviceInfo& di) {
+    Entry k = key_of(0, detectors, 0, levels, vmax, di);
+    k.kind = 1;
+    return k;
 }
 
 int chunk_count(int64_t lines, int32_t chunk_lines) {
@@ -204,6 +220,31 @@ bool tuned_plan(int64_t lines, int32_t detectors, int32_t bands, int32_t levels,
         return false;
     *plan = found;
     return true;
+}
+
+bool tuned_batch_shape(int32_t detectors, int32_t levels, int vmax, const DeviceInfo& di,
+                       rc_plan* plan) {
+    const Entry k = batch_key(detectors, levels, vmax, di);
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_loaded_locked();
+    auto it = std::find_if(g_cache.begin(), g_cache.end(),
+                           [&](const Entry& e) { return same_class(e, k); });
+    if (it == g_cache.end()) return false;
+    *plan = it->plan;
+    return true;
+}
+
+void store_batch_shape(int32_t detectors, int32_t levels, int vmax, const DeviceInfo& di,
+                       const rc_plan& plan, double us) {
+    Entry ent = batch_key(detectors, levels, vmax, di);
+    ent.plan = plan;
+    ent.us = us;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_loaded_locked();
+    auto it = std::find_if(g_cache.begin(), g_cache.end(),
+                           [&](const Entry& x) { return same_class(x, ent); });
+    if (it != g_cache.end()) *it = ent;
+    else g_cache.push_back(ent);
 }
 
 namespace {

@@ -167,16 +167,24 @@ C, T, I, O, S = 0x100000, 0x200000, 0x300000, 0x400000, 0x1000000
     [_req(C, I, T, O), _req(C + S, I + S, T + S, O)],     # two requests write one out
     [_req(C, I, T, O), _req(C + S, O, T + S, O + S)],     # output of one is input of another
     [_req(C, I, T, O), _req(C + S, I + S, T, O + S)],     # shared LUT written twice
+    [_req(C, I, T, C)],                                   # out is its own coeffs
+    [_req(C, I, T, C + 64)],                              # out overlaps its own coeffs
+    [_req(C, I, T, T + 16)],                              # out overlaps its own LUT
 ])
 def test_batch_rejects(reqs):
     arr = (rc.Request * len(reqs))(*reqs)
     h = ctypes.c_void_p()
     assert L.rc_batch_create(arr, len(reqs), 0, ctypes.byref(h)) == rc.RC_EINVAL
     assert not h.value
+    # The tuner validates the same way, before it touches the device.
+    n = ctypes.c_int32(-1)
+    assert L.rc_batch_tune(arr, len(reqs), 0, ctypes.byref(n), None) == rc.RC_EINVAL
+    assert n.value == 0
 
 
 def test_batch_null_args():
     h = ctypes.c_void_p()
+    assert L.rc_batch_tune(None, 3, 0, None, None) == rc.RC_EINVAL
     assert L.rc_batch_create(None, 3, 0, ctypes.byref(h)) == rc.RC_EINVAL
     assert L.rc_batch_create(None, -1, 0, ctypes.byref(h)) == rc.RC_EINVAL
     assert L.rc_batch_run(None, None) == rc.RC_EINVAL
@@ -260,3 +268,24 @@ def test_ws_bytes_host():
     assert rc.rc_correct_ws_bytes(100, 2, 1024) == 0
     assert rc.rc_correct_ws_bytes(100, 2, 8193) == 0
     assert rc.rc_correct_ws_bytes(0, 2, 4096) == 0
+
+
+def test_tune_cache_reads_json_with_spaces(tmp_path):
+    """Plan-cache lines may come from any JSON writer (spaces after colons);
+    batch entries keep their kind through a save and a reload."""
+    import json
+    entry = {"arch": "gfx950", "cus": 256, "levels": 4096, "dclass": 12, "nclass": 0,
+             "bands": 0, "vmax": 4, "path": rc.RC_PATH_DENSE, "strip": 128, "vec": 4,
+             "threads": 1024, "unroll": 4, "chunks": 1, "xcd_remap": 1, "nontemporal": 0,
+             "strips": 0, "lane_map": 0, "kind": 1, "us": 12.5}
+    src = tmp_path / "in.json"
+    src.write_text(json.dumps(entry) + "\n" + json.dumps(dict(entry, kind=7)) + "\n")
+    try:
+        assert rc.rc_tune_load(str(src)) == 1  # kind 7 is not a valid entry
+        out = tmp_path / "out.json"
+        assert rc.rc_tune_save(str(out)) == 1
+        saved = json.loads(out.read_text().splitlines()[0])
+        assert saved["kind"] == 1 and saved["path"] == rc.RC_PATH_DENSE and saved["strip"] == 128
+        assert rc.rc_tune_load(str(out)) == 1
+    finally:
+        rc.rc_tune_load()

@@ -1,6 +1,8 @@
 """Batched execution (persistent kernel + hipGraph) against the oracle and
 against the same requests run alone, bit-exact, over repeated graph replays
 with eager work in between."""
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -142,3 +144,93 @@ def test_batch_workload3_sample():
         assert np.array_equal(to_host_u16(lut), lw)
         assert np.array_equal(to_host_u16(out), w)
     batch.close()
+
+
+def test_batch_tuned(jobs):
+    """rc_batch_tune times candidate tile shapes per request class on the
+    batch kernel; the batch then takes every request's shape from those
+    entries, and stays bit-exact."""
+    tensors = [(j.c_t, j.dn_t, j.lut_t, j.out_t) for j in jobs]
+    try:
+        classes = rc.batch_tune(tensors)
+        torch.cuda.synchronize()
+        with_px = [j for j in jobs if j.spec[0] * j.spec[1] * j.spec[2] > 0]
+        assert 1 <= classes <= len(with_px)
+        for j in jobs:
+            j.reset()  # the tuning runs corrected the in-place request repeatedly
+        torch.cuda.synchronize()
+        batch = rc.Batch(tensors)
+        info = batch.info()
+        assert info["tuned"] == len(with_px)
+        assert info["fused"] + (info["lut_gather_entries"] > 0) >= 1
+        for replay in range(2):
+            batch.run()
+            torch.cuda.synchronize()
+            for j in jobs:
+                j.check(f"tuned, replay {replay}")
+            for j in jobs:
+                j.reset()
+            torch.cuda.synchronize()
+        batch.close()
+    finally:
+        rc.rc_tune_load()  # drop the in-memory batch entries
+
+
+def _vmax(j):
+    """The batch's pixels per lane bound for a job (4, 2 or 1), as librc
+    derives it from the detector count and the image alignment."""
+    D = j.spec[2]
+    al = j.dn_t.data_ptr() | j.out_t.data_ptr()
+    if D % 4 == 0 and al % 8 == 0:
+        return 4
+    if D % 2 == 0 and al % 4 == 0:
+        return 2
+    return 1
+
+
+@pytest.mark.parametrize("path,strip", [(rc.RC_PATH_DENSE, 128), (rc.RC_PATH_DENSE, 512),
+                                        (rc.RC_PATH_PACKED, 64), (rc.RC_PATH_LDS, 16),
+                                        (rc.RC_PATH_L2, 64)])
+def test_batch_forced_shapes(jobs, tmp_path, path, strip):
+    """Batch entries of the plan cache decide each request's tile shape: each
+    mode (dense, packed and raw LDS tiles built from the coefficients, and
+    the L2 path), forced for every request through a cache file, stays
+    bit-exact over two replays."""
+    props = torch.cuda.get_device_properties(dev())
+    arch = props.gcnArchName.split(":")[0]
+    lines, seen = [], set()
+    for j in jobs:
+        B, N, D, L = j.spec[:4]
+        if B * N * D == 0:
+            continue
+        key = (L, max(0, (D - 1).bit_length()), _vmax(j))
+        if key in seen:
+            continue
+        seen.add(key)
+        lines.append(json.dumps({
+            "arch": arch, "cus": props.multi_processor_count, "levels": key[0],
+            "dclass": key[1], "nclass": 0, "bands": 0, "vmax": key[2], "path": path,
+            "strip": strip, "vec": key[2], "threads": 1024, "unroll": 4, "chunks": 1,
+            "xcd_remap": 1, "nontemporal": 0, "strips": 0, "lane_map": 0, "kind": 1,
+            "us": 1.0}))
+    cache = tmp_path / "batch_cache.json"
+    cache.write_text("\n".join(lines) + "\n")
+    try:
+        assert rc.rc_tune_load(str(cache)) == len(lines)
+        for j in jobs:
+            j.reset()
+        torch.cuda.synchronize()
+        batch = rc.Batch([(j.c_t, j.dn_t, j.lut_t, j.out_t) for j in jobs])
+        info = batch.info()
+        assert info["tuned"] == sum(1 for j in jobs if j.spec[0] * j.spec[1] * j.spec[2] > 0)
+        for replay in range(2):
+            batch.run()
+            torch.cuda.synchronize()
+            for j in jobs:
+                j.check(f"path {path} strip {strip}, replay {replay}")
+            for j in jobs:
+                j.reset()
+            torch.cuda.synchronize()
+        batch.close()
+    finally:
+        rc.rc_tune_load()
