@@ -30,8 +30,8 @@ PROFILES = os.path.join(ROOT, "profiles")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", type=int, default=2, choices=(0, 1, 2))
     ap.add_argument("--no-scenes", action="store_true",
                     help="skip the other single-scene workload (1 or 2)")
@@ -915,14 +915,14 @@ def main():
     head = measure_scene(args, torch, rc, dev, gen.workload(args.workload), args.steps,
                          args.warmup, args.cpu_seconds, not args.no_verify,
                          not args.no_cpu_baseline)
-    # The other single-scene workloads, each with its own roofline (10 timed
-    # steps, bit-exact check, no CPU timing).
+    # The other single-scene workloads, each with its own roofline (20 warm-up
+    # and 20 timed steps, bit-exact check, no CPU timing).
     scenes = []
     if not args.no_scenes:
         for w in (1, 2):
             if w == args.workload:
                 continue
-            r = measure_scene(args, torch, rc, dev, gen.workload(w), 10, 3, 0.0,
+            r = measure_scene(args, torch, rc, dev, gen.workload(w), 20, 20, 0.0,
                               not args.no_verify, False)
             r.pop("cpu_baseline")
             scenes.append(r)
