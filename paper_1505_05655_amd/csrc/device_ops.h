@@ -321,6 +321,23 @@ __device__ __forceinline__ uint32_t g_dense(uint32_t dnv, uint32_t top, int logW
     return clamp0(u, (int)top);
 }
 
+// As g_dense, for a strip with blocks the dense form cannot hold: a level of
+// such a block (header kDenseBad) reads the LUT row in global memory.
+__device__ __forceinline__ uint32_t g_dense_checked(uint32_t dnv, uint32_t top, int logW,
+                                                    uint32_t p8, uint32_t h2,
+                                                    const uint16_t* row) {
+    const uint32_t v = dnv < top ? dnv : top;
+    const uint32_t blk = v >> 6;
+    const int h = *(lds_i16*)(uintptr_t)((blk << (logW + 1)) + h2);
+    if (h == (int)kDenseBad) return row[v];
+    const uint64_t z = *(lds_u64*)(uintptr_t)((blk << (logW + 3)) + p8);
+    const uint64_t sh = z << (v & 63u);
+    int u = (int)(v << ((uint32_t)z & 1u)) + h;
+    u = bcnt_acc((uint32_t)(sh >> 32), u);
+    u = bcnt_acc((uint32_t)sh, u);
+    return clamp0(u, (int)top);
+}
+
 // Encodes block `blk` (n entries, 1..64) of a LUT row: e holds the entries
 // two per word (entry 2k in the low half of e[k]). Returns false when the
 // block is not encodable.
@@ -638,10 +655,16 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
                         return g_dense(d, top, logW, p * 8u, hb + p * 2u);
                     }, pass_adv);
             } else {
+                // Some blocks of the strip (or, with the flag's word, block 0
+                // of its first position) are not held in dense form: their
+                // levels read the global LUT row, every other level decodes.
                 const uint16_t* lrow = strip_lut + (size_t)j * Lz;
                 stream_lines<VEC, UNROLL, NT>(
-                    rin, rout, vo, line_stride, passes,
-                    [&](int k, uint32_t d) { return g_glb(lrow + (size_t)k * Lz, d, top); }, pass_adv);
+                    rin, rout, vo, line_stride, passes, [&](int k, uint32_t d) {
+                        const uint32_t p = (uint32_t)((k << logq) + lane);
+                        return g_dense_checked(d, top, logW, p * 8u, hb + p * 2u,
+                                               lrow + (size_t)k * Lz);
+                    }, pass_adv);
             }
         }
         __syncthreads();  // the tile may be restaged next
