@@ -63,8 +63,9 @@ __global__ __launch_bounds__(256) void k_batch_encode(const BatchReq* __restrict
         const int NB = (q.levels + 63) >> 6;
         const double* a = q.coeffs + row * 4;
         const size_t o = (size_t)b * (size_t)NB * (size_t)q.detectors + (size_t)d;
-        encode_row_wave(a[0], a[1], a[2], a[3], q.levels, q.lut + row * (int64_t)q.levels,
-                        q.lut_vec != 0, q.planes + o, q.heads + o, (size_t)q.detectors);
+        encode_row_wave(q.levels, RowFromCoeffs{a[0], a[1], a[2], a[3], (double)q.levels},
+                        q.lut + row * (int64_t)q.levels, q.lut_vec != 0, q.planes + o, q.heads + o,
+                        (size_t)q.detectors);
     }
 }
 

@@ -820,21 +820,21 @@ __device__ __forceinline__ void store_lut8(uint16_t* dst, const uint32_t* e, int
     }
 }
 
-// One LUT row evaluated from its calibration coefficients by one wave,
-// written to `dst` (L entries) and encoded in the dense form: block blk's
-// plane and header go to planes[blk * stride] and heads[blk * stride] (the
+// One LUT row encoded in the dense form by one wave: block blk's plane and
+// header go to planes[blk * stride] and heads[blk * stride] (the
 // [band][block][detector] layout of a dense workspace); a block the form
-// cannot hold gets the header kDenseBad. 8 blocks per pass: lane 8g + q
-// computes levels 64 (8 r + g) + 8q .. + 7, so a pass stores 1 KiB of the
-// row contiguously; the 8 lanes of a block decide its form (the cases of
-// dense_encode) with xor-shuffles inside their group and OR their step bits
-// together. Every lane of the wave must call it.
-__device__ __forceinline__ void encode_row_wave(double a0, double a1, double a2, double a3, int L,
-                                                uint16_t* dst, bool lut_vec, uint64_t* planes,
-                                                int16_t* heads, size_t stride) {
+// cannot hold gets the header kDenseBad. src(v0, n, e) gives the n <= 8
+// entries from level v0 (evaluated from coefficients, or read from a LUT
+// row); with dst they are also written there (L entries). 8 blocks per
+// pass: lane 8g + q takes levels 64 (8 r + g) + 8q .. + 7, so a pass reads
+// or stores 1 KiB of the row contiguously; the 8 lanes of a block decide its
+// form (the cases of dense_encode) with xor-shuffles inside their group and
+// OR their step bits together. Every lane of the wave must call it.
+template <typename Src>
+__device__ __forceinline__ void encode_row_wave(int L, Src src, uint16_t* dst, bool lut_vec,
+                                                uint64_t* planes, int16_t* heads, size_t stride) {
     const int NB = (L + 63) >> 6;
     const int top = L - 1;
-    const double lim = (double)L;
     const int lane = (int)(threadIdx.x & 63);
     const int g = lane >> 3, q = lane & 7;
     const int rounds = (NB + 7) >> 3;
@@ -856,9 +856,8 @@ __device__ __forceinline__ void encode_row_wave(double a0, double a1, double a2,
         const int v0 = vb + (q << 3);
         const int n = max(0, min(8, L - v0));
         int e[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) e[k] = k < n ? (int)lut_entry(a0, a1, a2, a3, v0 + k, lim) : 0;
-        if (n > 0) {
+        src(v0, n, e);
+        if (dst && n > 0) {
             uint32_t w[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) w[k] = (uint32_t)e[k];
@@ -937,6 +936,16 @@ __device__ __forceinline__ void encode_row_wave(double a0, double a1, double a2,
         }
     }
 }
+
+// Entry source for encode_row_wave: a row evaluated from its calibration
+// coefficients.
+struct RowFromCoeffs {
+    double a0, a1, a2, a3, lim;
+    __device__ __forceinline__ void operator()(int v0, int n, int (&e)[8]) const {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) e[k] = k < n ? (int)lut_entry(a0, a1, a2, a3, v0 + k, lim) : 0;
+    }
+};
 
 // Computes the LUT rows of band b, detectors [d0, d0 + weff) from their
 // calibration coefficients straight into the LDS tile (raw or packed layout,
