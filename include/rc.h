@@ -424,9 +424,11 @@ rc_status rc_batch_create(const rc_request* reqs, int32_t n, int32_t flags, rc_b
  * requests with pixels are grouped by (levels, ceil(log2 detectors), largest
  * usable vector width); for each class, candidate shapes (LDS mode, strip
  * width, pixels per lane) run the class's requests as one batch, launched
- * directly on `stream` (one warm-up run, then 3 timed with HIP events), and
- * the fastest goes into the plan cache as that class's batch entry
- * (rc_tune_save persists it). effort 0 tries the two widest strips and two
+ * directly on `stream` (one warm-up run, then 3 timed with HIP events). The
+ * shape rc_batch_create would take without an entry runs first and is kept
+ * unless a candidate is at least 2 % faster; the result goes into the plan
+ * cache as that class's batch entry (rc_tune_save persists it). effort 0
+ * tries the two widest strips and two
  * vector widths per LDS mode; effort 1 one more of each. The runs write the
  * requests' lut and out exactly as rc_batch_run would. Validates as
  * rc_batch_create; synchronises; allocates (each candidate's tables).
