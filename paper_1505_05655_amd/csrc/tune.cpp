@@ -1,7 +1,7 @@
 // Autotuner and plan cache for the correction kernel.
 //
 // rc_tune times candidate launch shapes (path, strip width, pixels per lane,
-// workgroup size, unroll, line chunking, XCD remap, non-temporal hints) on
+// workgroup size, unroll, line chunking, XCD remap, cache policy) on
 // the caller's buffers with HIP events and keeps the fastest per shape
 // class. Shape class = (arch, CU count, levels, ceil(log2 detectors),
 // ceil(log2 lines), bands, largest usable vector width). Line chunking is
@@ -23,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "device_ops.h"
 #include "kernels.h"
 #include "rc.h"
 #include "runtime.h"
@@ -337,7 +338,7 @@ std::vector<rc_plan> candidates(int64_t lines, int32_t detectors, int32_t bands,
             for (int vec : vecs)
                 for (int threads : threads_l)
                     for (int unroll : unrolls)
-                        for (int nt = 0; nt < 3; ++nt)
+                        for (int nt = 0; nt < (effort ? kPolicies : 3); ++nt)
                             for (int k : ks) {
                                 if (vec == 8 && unroll != 4) continue;
                                 if (path == RC_PATH_DENSE && threads > kDenseMaxThreads) continue;
