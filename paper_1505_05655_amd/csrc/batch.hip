@@ -41,6 +41,150 @@
 
 namespace rc {
 
+// Lane exchanges inside groups of 8 lanes as DPP moves (VALU, no LDS):
+// quad_perm [1,0,3,2] and [2,3,0,1] swap with the lane at distance 1 and 2,
+// row_half_mirror (lane i <-> 7 - i) with one of the other quad, and
+// row_shl:1 reads the next lane of the 16-lane row.
+constexpr int kDppQuadXor1 = 0xB1;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRowShl1 = 0x101;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+
+// Minimum / maximum / OR over the 8 lanes of x's group, returned on all 8.
+__device__ __forceinline__ int group8_min(int x) {
+    x = min(x, dpp_move<kDppQuadXor1>(x));
+    x = min(x, dpp_move<kDppQuadXor2>(x));
+    return min(x, dpp_move<kDppHalfMirror>(x));
+}
+__device__ __forceinline__ int group8_max(int x) {
+    x = max(x, dpp_move<kDppQuadXor1>(x));
+    x = max(x, dpp_move<kDppQuadXor2>(x));
+    return max(x, dpp_move<kDppHalfMirror>(x));
+}
+__device__ __forceinline__ uint32_t group8_or(uint32_t x) {
+    x |= (uint32_t)dpp_move<kDppQuadXor1>((int)x);
+    x |= (uint32_t)dpp_move<kDppQuadXor2>((int)x);
+    return x | (uint32_t)dpp_move<kDppHalfMirror>((int)x);
+}
+
+template <typename Src>
+__device__ __forceinline__ void encode_row_wave(int L, Src src, uint16_t* dst, bool lut_vec,
+                                                uint64_t* planes, int16_t* heads, size_t stride) {
+    const int NB = (L + 63) >> 6;
+    const int top = L - 1;
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = lane >> 3, q = lane & 7;
+    const int rounds = (NB + 7) >> 3;
+    constexpr int kBig = 1 << 20;
+    for (int r = 0; r < rounds; ++r) {
+        const int blk = (r << 3) + g;
+        const int vb = blk << 6;
+        const int cnt = min(64, L - vb);  // entries of the block (<= 0 past the row)
+        const int v0 = vb + (q << 3);
+        const int n = max(0, min(8, L - v0));
+        const u32x4 raw = src.fetch(v0, n);
+        int e[8];
+        e[0] = (int)(raw.x & 0xffffu);
+        e[1] = (int)(raw.x >> 16);
+        e[2] = (int)(raw.y & 0xffffu);
+        e[3] = (int)(raw.y >> 16);
+        e[4] = (int)(raw.z & 0xffffu);
+        e[5] = (int)(raw.z >> 16);
+        e[6] = (int)(raw.w & 0xffffu);
+        e[7] = (int)(raw.w >> 16);
+        if (dst && n > 0) {
+            uint32_t w[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) w[k] = (uint32_t)e[k];
+            store_lut8(dst + v0, w, n, lut_vec);
+        }
+        // Steps t = 8q + k (entry t+1 minus entry t) inside the block.
+        const int nxt = dpp_move<kDppRowShl1>(e[0]);  // lane q + 1's first entry (q < 7)
+        int mn = kBig, mx = -kBig, smin = kBig, smax = -kBig, first = 64;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int t = (q << 3) + k;
+            const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
+            if (t + 1 < cnt) {
+                mn = min(mn, eb - ea);
+                mx = max(mx, eb - ea);
+                if (eb != 0 && ea != top) {
+                    smin = min(smin, eb - ea);
+                    smax = max(smax, eb - ea);
+                }
+                if (ea == 0 && eb != 0) first = min(first, t + 1);
+            }
+        }
+        mn = group8_min(mn);
+        mx = group8_max(mx);
+        smin = group8_min(smin);
+        smax = group8_max(smax);
+        first = min(group8_min(first), max(cnt, 0));
+        const int e0 = group8_max(q == 0 ? e[0] : -1);  // entries are >= 0
+        int last = -1;  // entry cnt - 1, held by one lane of the group
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((q << 3) + k == cnt - 1) last = e[k];
+        last = group8_max(last);
+        bool ok = true;
+        int s = 0, u0 = e0, kind = 0;  // 0 constant, 1 unsaturated, 2 transition
+        if (cnt > 1 && mn < 0) {
+            ok = false;
+        } else if (cnt <= 1 || e0 == top || last == 0) {
+            kind = 0;
+        } else if (e0 != 0 && last != top) {
+            kind = 1;
+            s = max(0, mx - 1);
+            ok = s <= 1 && mn >= s;
+        } else {
+            kind = 2;
+            s = max(0, smax - 1);
+            ok = s <= 1 && smin >= s;
+            if (e0 == 0) u0 = -(s + 1) * (first - 1);
+        }
+        uint32_t lo8 = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
+            int bit = 0;
+            if ((q << 3) + k + 1 < cnt) {
+                if (kind == 1) bit = eb - ea - s;
+                if (kind == 2) bit = (eb != 0 && ea != top) ? eb - ea - s : 1;
+            }
+            lo8 |= (uint32_t)(bit & 1) << k;
+        }
+        // Bit t+1 of the block word = b_t: this lane's bits start at 8q+1.
+        const uint64_t mine = (uint64_t)lo8 << ((q << 3) + 1);
+        const uint32_t blo = group8_or((uint32_t)mine), bhi = group8_or((uint32_t)(mine >> 32));
+        const uint64_t bits = ((uint64_t)bhi << 32) | blo;
+        const uint64_t z = (~(__builtin_bitreverse64(bits) << 1) & ~(uint64_t)1) | (uint64_t)s;
+        const int H = u0 + __builtin_popcountll(bits) - 63 - 64 * (s + 1) * blk - s;
+        if (H <= (int)kDenseBad || H > 32767) ok = false;
+        if (q == 0 && blk < NB) {
+            planes[(size_t)blk * stride] = ok ? z : 0;
+            heads[(size_t)blk * stride] = ok ? (int16_t)H : kDenseBad;
+        }
+    }
+}
+
+// Entry source for encode_row_wave: a row evaluated from its calibration
+// coefficients.
+struct RowFromCoeffs {
+    double a0, a1, a2, a3, lim;
+    __device__ __forceinline__ u32x4 fetch(int v0, int n) const {
+        uint32_t e[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) e[k] = k < n ? lut_entry(a0, a1, a2, a3, v0 + k, lim) : 0u;
+        return u32x4{e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16),
+                     e[6] | (e[7] << 16)};
+    }
+};
+
 // Request r owns LUT rows [rprefix[r], rprefix[r + 1]) (band-major, detector
 // fastest); one wave per row.
 __global__ __launch_bounds__(256) void k_batch_encode(const BatchReq* __restrict__ reqs,

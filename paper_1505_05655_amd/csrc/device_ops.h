@@ -823,130 +823,13 @@ __device__ __forceinline__ void store_lut8(uint16_t* dst, const uint32_t* e, int
 // One LUT row encoded in the dense form by one wave: block blk's plane and
 // header go to planes[blk * stride] and heads[blk * stride] (the
 // [band][block][detector] layout of a dense workspace); a block the form
-// cannot hold gets the header kDenseBad. src(v0, n, e) gives the n <= 8
-// entries from level v0 (evaluated from coefficients, or read from a LUT
-// row); with dst they are also written there (L entries). 8 blocks per
+// cannot hold gets the header kDenseBad. src.fetch(v0, n) gives the n <= 8
+// entries from level v0 packed two per word (evaluated from coefficients,
+// or read from a LUT row); with dst they are also written there (L entries). 8 blocks per
 // pass: lane 8g + q takes levels 64 (8 r + g) + 8q .. + 7, so a pass reads
 // or stores 1 KiB of the row contiguously; the 8 lanes of a block decide its
 // form (the cases of dense_encode) with xor-shuffles inside their group and
 // OR their step bits together. Every lane of the wave must call it.
-template <typename Src>
-__device__ __forceinline__ void encode_row_wave(int L, Src src, uint16_t* dst, bool lut_vec,
-                                                uint64_t* planes, int16_t* heads, size_t stride) {
-    const int NB = (L + 63) >> 6;
-    const int top = L - 1;
-    const int lane = (int)(threadIdx.x & 63);
-    const int g = lane >> 3, q = lane & 7;
-    const int rounds = (NB + 7) >> 3;
-    auto gmin = [](int x) {
-        x = min(x, __shfl_xor(x, 1, 64));
-        x = min(x, __shfl_xor(x, 2, 64));
-        return min(x, __shfl_xor(x, 4, 64));
-    };
-    auto gmax = [](int x) {
-        x = max(x, __shfl_xor(x, 1, 64));
-        x = max(x, __shfl_xor(x, 2, 64));
-        return max(x, __shfl_xor(x, 4, 64));
-    };
-    constexpr int kBig = 1 << 20;
-    for (int r = 0; r < rounds; ++r) {
-        const int blk = (r << 3) + g;
-        const int vb = blk << 6;
-        const int cnt = min(64, L - vb);  // entries of the block (<= 0 past the row)
-        const int v0 = vb + (q << 3);
-        const int n = max(0, min(8, L - v0));
-        int e[8];
-        src(v0, n, e);
-        if (dst && n > 0) {
-            uint32_t w[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) w[k] = (uint32_t)e[k];
-            store_lut8(dst + v0, w, n, lut_vec);
-        }
-        // Steps t = 8q + k (entry t+1 minus entry t) inside the block.
-        const int nxt = __shfl_down(e[0], 1, 64);
-        int mn = kBig, mx = -kBig, smin = kBig, smax = -kBig, first = 64;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int t = (q << 3) + k;
-            const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
-            if (t + 1 < cnt) {
-                mn = min(mn, eb - ea);
-                mx = max(mx, eb - ea);
-                if (eb != 0 && ea != top) {
-                    smin = min(smin, eb - ea);
-                    smax = max(smax, eb - ea);
-                }
-                if (ea == 0 && eb != 0) first = min(first, t + 1);
-            }
-        }
-        mn = gmin(mn);
-        mx = gmax(mx);
-        smin = gmin(smin);
-        smax = gmax(smax);
-        first = min(gmin(first), max(cnt, 0));
-        const int e0 = __shfl(e[0], lane & ~7, 64);
-        int last = -1;  // entry cnt - 1, held by one lane of the group
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if ((q << 3) + k == cnt - 1) last = e[k];
-        last = gmax(last);
-        bool ok = true;
-        int s = 0, u0 = e0, kind = 0;  // 0 constant, 1 unsaturated, 2 transition
-        if (cnt > 1 && mn < 0) {
-            ok = false;
-        } else if (cnt <= 1 || e0 == top || last == 0) {
-            kind = 0;
-        } else if (e0 != 0 && last != top) {
-            kind = 1;
-            s = max(0, mx - 1);
-            ok = s <= 1 && mn >= s;
-        } else {
-            kind = 2;
-            s = max(0, smax - 1);
-            ok = s <= 1 && smin >= s;
-            if (e0 == 0) u0 = -(s + 1) * (first - 1);
-        }
-        uint32_t lo8 = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
-            int bit = 0;
-            if ((q << 3) + k + 1 < cnt) {
-                if (kind == 1) bit = eb - ea - s;
-                if (kind == 2) bit = (eb != 0 && ea != top) ? eb - ea - s : 1;
-            }
-            lo8 |= (uint32_t)(bit & 1) << k;
-        }
-        // Bit t+1 of the block word = b_t: this lane's bits start at 8q+1.
-        const uint64_t mine = (uint64_t)lo8 << ((q << 3) + 1);
-        uint32_t blo = (uint32_t)mine, bhi = (uint32_t)(mine >> 32);
-#pragma unroll
-        for (int m = 1; m < 8; m <<= 1) {
-            blo |= (uint32_t)__shfl_xor((int)blo, m, 64);
-            bhi |= (uint32_t)__shfl_xor((int)bhi, m, 64);
-        }
-        const uint64_t bits = ((uint64_t)bhi << 32) | blo;
-        const uint64_t z = (~(__builtin_bitreverse64(bits) << 1) & ~(uint64_t)1) | (uint64_t)s;
-        const int H = u0 + __builtin_popcountll(bits) - 63 - 64 * (s + 1) * blk - s;
-        if (H <= (int)kDenseBad || H > 32767) ok = false;
-        if (q == 0 && blk < NB) {
-            planes[(size_t)blk * stride] = ok ? z : 0;
-            heads[(size_t)blk * stride] = ok ? (int16_t)H : kDenseBad;
-        }
-    }
-}
-
-// Entry source for encode_row_wave: a row evaluated from its calibration
-// coefficients.
-struct RowFromCoeffs {
-    double a0, a1, a2, a3, lim;
-    __device__ __forceinline__ void operator()(int v0, int n, int (&e)[8]) const {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) e[k] = k < n ? (int)lut_entry(a0, a1, a2, a3, v0 + k, lim) : 0;
-    }
-};
-
 // Computes the LUT rows of band b, detectors [d0, d0 + weff) from their
 // calibration coefficients straight into the LDS tile (raw or packed layout,
 // as the correction tile reads them) and, if `write_lut`, also into the
