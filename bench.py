@@ -14,6 +14,7 @@ import hashlib
 import json
 import os
 import platform
+import re
 import statistics
 import sys
 import time
@@ -626,10 +627,15 @@ def bench_serve(args, torch, rc, dev):
 
 
 def kernel_source_hash():
+    """Hash of the correction's sources with comments and whitespace removed,
+    so that counters stay attached to the code they were taken on."""
     h = hashlib.sha256()
     for f in ("device_ops.h", "lut_apply.hip", "api.cpp"):
-        with open(os.path.join(ROOT, "paper_1505_05655_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1505_05655_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

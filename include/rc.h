@@ -99,11 +99,12 @@ typedef enum {
                            plus 2-bit steps (2.5 bits/entry, exact); a tile whose rows have a
                            step outside 0..3 gathers from the global LUT instead */
     RC_PATH_DENSE = 3   /* strip LUT rows staged in LDS as 64-level blocks of a 16-bit header
-                           (base, slope s in 0..3) plus one bit per step (step s or s + 1),
+                           plus one bit per step (slope s in 0..1: each step s or s + 1),
                            saturated runs extrapolated and clamped back (1.25 bits/entry,
-                           exact; levels <= 8192); a tile with a row that does not fit this
-                           form (decreasing, or steps spread over more than two values
-                           between unsaturated entries) gathers from the global LUT instead */
+                           exact; levels <= 8192, at most 512 threads); the levels of a block
+                           that does not fit this form (decreasing, or steps spread over more
+                           than two values, or steps of 3 or more between unsaturated
+                           entries) are read from the global LUT instead */
 } rc_path;
 
 typedef struct {
@@ -114,7 +115,9 @@ typedef struct {
                             needs detectors % 8 == 0 and 16-byte aligned dn and out) */
     int32_t threads;     /* workgroup size: 256, 512 or 1024 (RC_PATH_DENSE: 256 or 512) */
     int32_t unroll;      /* lines in flight per lane: 4, 8 or 16 */
-    int32_t chunk_lines; /* lines per tile, >= 1 */
+    int32_t chunk_lines; /* lines per tile, >= 1; with an LDS path and a band whose bytes
+                            fit 32-bit offsets, a strip's ceil(lines / chunk_lines) tiles
+                            take its passes of lines in turn instead of contiguous ranges */
     int32_t xcd_remap;   /* 1: place neighbouring tiles on the same XCD */
     int32_t nontemporal; /* image cache policy: 0 default, 1 non-temporal loads and stores,
                             2 non-temporal stores, 3 sc0 loads + non-temporal stores,

@@ -43,7 +43,7 @@ struct ApplyParams {
 
 // Encodes every 64-level block of every LUT row into the dense form (planes
 // and headers, [bands][ceil(levels / 64)][detectors]; a block that does not
-// fit the form gets bit 0 of its plane set).
+// fit the form gets the header kDenseBad).
 hipError_t launch_dense_encode(const uint16_t* lut, int32_t bands, int32_t detectors,
                                int32_t levels, uint64_t* planes, int16_t* heads,
                                hipStream_t stream);

@@ -1,11 +1,14 @@
 // Correction kernel (§I "Image Correction"): out[b][n][d] = lut[b][d][min(dn, L-1)].
 //
-// One workgroup per tile (band, strip of W detectors, chunk of lines). The
-// raw LDS path stages the strip's W LUT rows into LDS level-major; the packed
-// LDS path stages them as 2.5-bit step codes so strips are 6.4x wider; both
-// then stream the chunk's lines through coalesced vector loads/stores. The
-// L2 path gathers straight from the global LUT and orders tiles so that the
-// CUs of one XCD share a strip whose LUT rows stay in that XCD's L2.
+// One workgroup per tile (band, strip of detectors, chunk of lines). The raw
+// LDS path stages the strip's LUT rows into LDS level-major; the packed and
+// dense LDS paths stage them as 2.5-bit and 1.25-bit step codes, so strips
+// are 6.4x and 12.8x wider (the dense blocks come from k_dense_encode's
+// workspace, or are encoded by the tile); all then stream the chunk's lines
+// (contiguous, or every k-th pass of the band) through coalesced vector
+// loads/stores. The L2 path gathers straight from the global LUT and orders
+// tiles so that the CUs of one XCD share a strip whose LUT rows stay in that
+// XCD's L2.
 #include "device_ops.h"
 #include "kernels.h"
 
@@ -144,7 +147,7 @@ int unroll_index(int u) { return u == 4 ? 0 : (u == 8 ? 1 : 2); }
 
 hipError_t prepare_apply_kernels(size_t bytes, size_t* usable) {
     // A kernel's dynamic LDS limit is the CU's LDS minus its own static LDS
-    // (e.g. the word __syncthreads_or reduces through).
+    // (none in these kernels; the dense mode relies on that).
     const Table& t = table();
     size_t worst_static = 0;
     for (int v = 0; v < 4; ++v)
