@@ -48,10 +48,14 @@ __global__ __launch_bounds__(256) void k_lut_build(const double* __restrict__ co
 }
 
 // Wave w of the grid evaluates row w (then w + number of waves, ...), 512
-// levels per pass.
+// levels per pass. nt: non-temporal 16-byte stores, for LUTs larger than the
+// L2 caches. Left in the caches, such a LUT is only evicted, dirty, while the
+// correction that follows streams its image (measured on the 3 x 50000 x 6000
+// scene: that correction took 0.83 ms after a cacheable build and 0.77 ms
+// after a non-temporal one; the build itself 39.5 and 37.0 us).
 __global__ __launch_bounds__(256) void k_lut_build_rows(const double* __restrict__ coeffs,
                                                         int64_t rows, int32_t levels, int32_t vec,
-                                                        uint16_t* __restrict__ lut) {
+                                                        int32_t nt, uint16_t* __restrict__ lut) {
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const double lim = (double)levels;
@@ -73,7 +77,8 @@ __global__ __launch_bounds__(256) void k_lut_build_rows(const double* __restrict
                 q.y = e[2] | (e[3] << 16);
                 q.z = e[4] | (e[5] << 16);
                 q.w = e[6] | (e[7] << 16);
-                *(u32x4*)dst = q;  // cacheable: the correction reads the LUT next
+                if (nt) __builtin_nontemporal_store(q, (u32x4*)dst);
+                else *(u32x4*)dst = q;
             } else {
                 for (int k = 0; k < n; ++k) dst[k] = (uint16_t)lut_entry(a0, a1, a2, a3, v0 + k, lim);
             }
@@ -87,8 +92,10 @@ hipError_t launch_lut_build(const double* coeffs, int64_t rows, int32_t levels, 
     if (levels >= 512) {
         int64_t blocks = (rows + 3) / 4;  // one wave per row
         if (blocks > (int64_t)1 << 20) blocks = (int64_t)1 << 20;  // grid-stride beyond this
+        // Non-temporal above the GPU's aggregate L2 (8 XCDs x 4 MiB).
+        const int nt = (double)rows * (double)levels * 2.0 > (double)(32u << 20) ? 1 : 0;
         hipLaunchKernelGGL(k_lut_build_rows, dim3((unsigned)blocks), dim3(256), 0, stream, coeffs,
-                           rows, levels, vec ? 1 : 0, lut);
+                           rows, levels, vec ? 1 : 0, nt, lut);
         return hipGetLastError();
     }
     const int32_t chunks = (levels + 7) / 8;
