@@ -113,7 +113,10 @@ typedef struct {
                             for W detectors */
     int32_t vec;         /* pixels per lane per line: 1, 2, 4 or 8 (8: 16-byte image accesses,
                             needs detectors % 8 == 0 and 16-byte aligned dn and out) */
-    int32_t threads;     /* workgroup size: 256, 512 or 1024 (RC_PATH_DENSE: 256 or 512) */
+    int32_t threads;     /* threads that stream the image: 256, 512 or 1024 (RC_PATH_DENSE: 256
+                            or 512). When there are no more tiles than CUs, RC_PATH_LDS and
+                            RC_PATH_PACKED tiles launch 1024 threads and RC_PATH_DENSE tiles 512;
+                            the waves beyond `threads` only help stage the strip */
     int32_t unroll;      /* lines in flight per lane: 4, 8 or 16 */
     int32_t chunk_lines; /* lines per tile, >= 1; with an LDS path and a band whose bytes
                             fit 32-bit offsets, a strip's ceil(lines / chunk_lines) tiles

@@ -318,7 +318,20 @@ rc_status check_plan(const rc_plan& plan, int64_t lines, int32_t detectors, int3
     const int64_t chunks = (lines + plan.chunk_lines - 1) / plan.chunk_lines;
     int64_t tiles = 0;
     if (!mul_ok((int64_t)bands * strips, chunks, &tiles)) return RC_EINVAL;
-    if (tiles * plan.threads >= ((int64_t)1 << 32) || tiles > INT32_MAX) return RC_EINVAL;
+    // A tile alone on its CU stages its strip with more waves than stream:
+    // packing a 256 x 1024 strip with 4 waves (one per SIMD) is bound by
+    // instruction issue (49 us on the 4 x 12000 x 12000 scene, against 31 us
+    // with 16 waves); streaming with the plan's 256 threads stays faster than
+    // with 1024 (0.509 against 0.525 ms). The extra waves wait at the tile's
+    // barriers while the others stream.
+    int block = plan.threads;
+    if (di.cus > 0 && tiles <= di.cus) {
+        if (plan.path == RC_PATH_LDS || plan.path == RC_PATH_PACKED) block = 1024;
+        if (plan.path == RC_PATH_DENSE) block = kDenseMaxThreads;
+    }
+    if (tiles * block >= ((int64_t)1 << 32) || tiles > INT32_MAX) return RC_EINVAL;
+    p->threads = plan.threads;
+    p->block = std::max(block, plan.threads);
     p->pre_planes = nullptr;
     p->pre_heads = nullptr;
     p->lines = lines;

@@ -495,7 +495,7 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
                                            void* smem, bool lut_vec, bool dense,
                                            const uint64_t* pre_planes = nullptr,
                                            const int16_t* pre_heads = nullptr, int ci = 0,
-                                           int ck = 1) {
+                                           int ck = 1, int nst = 0) {
     constexpr int LOGVEC = log_vec<VEC>();
     const int W = 1 << logW;
     const int tid = threadIdx.x;
@@ -507,9 +507,10 @@ __device__ __forceinline__ void apply_tile(const uint16_t* dn, const uint16_t* _
     const int q = dense ? (weff >> LOGVEC) : (1 << logq);  // lanes per strip line
     const int row = tid / q;         // this thread's line within a pass
     const int lane = tid - row * q;
+    // Lines per pass, from the nst streaming threads (0: all of them).
     // Wave-uniform (the compiler cannot prove it through the division and
     // would otherwise wrap every buffer access in a waterfall loop).
-    const int rpp = __builtin_amdgcn_readfirstlane(nt / q);  // lines per pass
+    const int rpp = __builtin_amdgcn_readfirstlane((nst ? nst : nt) / q);
     // Threads past the last whole line, or past the strip, only stage.
     const bool streams = row < rpp && lane * VEC < weff;
     const int j = lane * VEC;

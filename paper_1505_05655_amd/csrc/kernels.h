@@ -39,6 +39,8 @@ struct ApplyParams {
     // (layout [bands][blocks][detectors]); NULL: each tile encodes its strip.
     const uint64_t* pre_planes;
     const int16_t* pre_heads;
+    int32_t threads;     // threads that stream the image (the plan's workgroup size)
+    int32_t block;       // threads launched: `threads`, or more whose waves only stage
 };
 
 // Encodes every 64-level block of every LUT row into the dense form (planes

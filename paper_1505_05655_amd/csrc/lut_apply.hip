@@ -59,7 +59,7 @@ __global__ __launch_bounds__(MODE == kDense ? kDenseMaxThreads : 1024) void k_ap
     }
     apply_tile<VEC, UNROLL, NT, MODE>(p.dn, p.lut, p.out, p.lines, p.detectors, p.levels,
                                        p.log_strip, b, d0, weff, n0, n1, smem, p.lut_vec != 0,
-                                       p.dense != 0, p.pre_planes, p.pre_heads, ci, ck);
+                                       p.dense != 0, p.pre_planes, p.pre_heads, ci, ck, p.threads);
 }
 
 // One thread per (row, 64-level block). Consecutive threads take the same
@@ -194,7 +194,7 @@ hipError_t launch_apply(const ApplyParams& p, const rc_plan& plan, size_t lds_by
     ApplyKernel k = table().k[vec_index(plan.vec)][unroll_index(plan.unroll)]
                              [plan.nontemporal * kModes + plan.path];
     if (!k) return hipErrorInvalidValue;  // combinations check_plan rejects
-    hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3((unsigned)plan.threads),
+    hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3((unsigned)p.block),
                        plan.path == RC_PATH_L2 ? 0 : lds_bytes, stream, p);
     return hipGetLastError();
 }

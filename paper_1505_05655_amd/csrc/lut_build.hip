@@ -49,10 +49,10 @@ __global__ __launch_bounds__(256) void k_lut_build(const double* __restrict__ co
 
 // Wave w of the grid evaluates row w (then w + number of waves, ...), 512
 // levels per pass. nt: non-temporal 16-byte stores, for LUTs larger than the
-// L2 caches. Left in the caches, such a LUT is only evicted, dirty, while the
-// correction that follows streams its image (measured on the 3 x 50000 x 6000
-// scene: that correction took 0.83 ms after a cacheable build and 0.77 ms
-// after a non-temporal one; the build itself 39.5 and 37.0 us).
+// L2 caches, which the correction after the build does not find there anyway
+// (on the 3 x 50000 x 6000 scene the correction after a build took 0.77 ms
+// instead of 0.83 ms on one GPU, and the same 0.82-0.84 ms either way on two
+// others; the build itself is not slower).
 __global__ __launch_bounds__(256) void k_lut_build_rows(const double* __restrict__ coeffs,
                                                         int64_t rows, int32_t levels, int32_t vec,
                                                         int32_t nt, uint16_t* __restrict__ lut) {
