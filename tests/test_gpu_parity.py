@@ -310,6 +310,33 @@ def test_dense_path(o, shape, rows):
     assert n >= 2
 
 
+@pytest.mark.parametrize("path", [rc.RC_PATH_LDS, rc.RC_PATH_PACKED, rc.RC_PATH_DENSE])
+def test_staging_waves_tile_count_boundary(o, path):
+    """Tiles alone on their CU launch more threads than stream (extra waves
+    only stage the strip); one tile more and the workgroup is the plan's.
+    Both sides of that boundary, and one tile below it, match the oracle."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    B, N, D, L = 1, 37, (cus + 1) * 4, 1024
+    coeffs, dn = pins.tiny_case(cus + path, B, N, D, L)
+    rng = np.random.default_rng(cus + 7 * path)
+    coeffs[..., 0] = rng.normal(0, L / 128, size=(B, D))
+    coeffs[..., 1] = rng.uniform(0.9, 1.1, size=(B, D))
+    coeffs[..., 2] = rng.normal(0, 0.05 / L, size=(B, D))
+    coeffs[..., 3] = 0.0
+    coeffs[0, 5] = [L - 1, -1.0, 0, 0]  # one row no compact form holds
+    _, want = expect(o, coeffs, dn, L)
+    lut_t = rc.lut_build(to_dev_f64(coeffs), L)
+    dn_t = to_dev_u16(dn)
+    for strips in (cus - 1, cus, cus + 1):
+        plan = rc.Plan(path=path, strip=16, vec=4, threads=256, unroll=4, chunk_lines=N,
+                       xcd_remap=1, nontemporal=0, strips=strips)
+        out = Guarded((B, N, D))
+        rc.correct(dn_t, lut_t, out=out.t, plan=plan)
+        torch.cuda.synchronize()
+        out.check_pads()
+        assert np.array_equal(out.host(), want), f"strips {strips}, plan {plan}"
+
+
 def test_dense_rejects_long_rows():
     dn = torch.zeros((1, 4, 64), dtype=torch.int16, device=dev())
     lut = torch.zeros((1, 64, 8200), dtype=torch.int16, device=dev())
