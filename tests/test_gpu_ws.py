@@ -36,8 +36,10 @@ def case(shape, rows, seed):
     return coeffs, dn
 
 
+# 2112 levels: 33 whole blocks, so the last group of 8 blocks a workgroup of
+# the encoder stages holds one block; 3000: a partial last block.
 SHAPES = [(3, 401, 1000, 4096), (1, 300, 520, 2048), (2, 77, 96, 8192), (1, 129, 333, 3000),
-          (2, 64, 200, 1024), (1, 5, 7, 4096)]
+          (2, 64, 200, 1024), (1, 5, 7, 4096), (1, 50, 45, 2112)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
