@@ -707,11 +707,24 @@ def measure_scene(args, torch, rc, dev, s, steps, warmup, cpu_seconds, verify, c
         rc.rc_correct_ws(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, ws_t,
                          ws_bytes, None, stream)
 
-    correct = correct_ws if ws_bytes else correct_plain
-    entry = "rc_correct_ws" if ws_bytes else "rc_correct"
+    def correct_pre():
+        rc.rc_correct_pre(dn_t, lut_t, s.lines, s.detectors, s.bands, s.levels, out_t, ws_t,
+                          ws_bytes, None, stream)
+
+    def build_plain():
+        rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
+
+    def build_ws():
+        rc.rc_lut_build_ws(c_t, s.bands, s.detectors, s.levels, lut_t, ws_t, ws_bytes, stream)
+
+    # Long LUT rows: the build also writes the LUT's dense encoding to the
+    # workspace, and the correction's tiles stage that (no encoding pass).
+    build = build_ws if ws_bytes else build_plain
+    correct = correct_pre if ws_bytes else correct_plain
+    entry = "rc_lut_build_ws + rc_correct_pre" if ws_bytes else "rc_lut_build + rc_correct"
 
     def step():
-        rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
+        build()
         correct()
 
     torch.cuda.synchronize()
@@ -725,7 +738,7 @@ def measure_scene(args, torch, rc, dev, s, steps, warmup, cpu_seconds, verify, c
     w0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
-        rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
+        build()
         ev[k][1].record(stream)
         correct()
         ev[k][2].record(stream)
@@ -737,8 +750,12 @@ def measure_scene(args, torch, rc, dev, s, steps, warmup, cpu_seconds, verify, c
 
     px = s.pixels
     lut_bytes = s.bands * s.detectors * s.levels * 2
-    apply_bytes = 4 * px + lut_bytes                      # 2 B read + 2 B written per pixel + LUT once
-    build_bytes = lut_bytes + s.bands * s.detectors * 32  # LUT written + coefficients read
+    # 2 B read + 2 B written per pixel + the LUT read once; with the
+    # workspace the LUT reaches the correction as its dense encoding (8-byte
+    # plane + 2-byte header per 64-level block), which the build writes.
+    enc_bytes = s.bands * s.detectors * -(-s.levels // 64) * 10 if ws_bytes else 0
+    apply_bytes = 4 * px + (enc_bytes if ws_bytes else lut_bytes)
+    build_bytes = lut_bytes + enc_bytes + s.bands * s.detectors * 32  # written + coefficients
     apply_avg = statistics.mean(apply_ms)
     achieved = apply_bytes / (apply_avg * 1e-3) / 1e9
 
@@ -751,7 +768,7 @@ def measure_scene(args, torch, rc, dev, s, steps, warmup, cpu_seconds, verify, c
             scratch.fill_(1)
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record(stream)
-        rc.rc_lut_build(c_t, s.bands, s.detectors, s.levels, lut_t, stream)
+        build()
         e[1].record(stream)
         correct()
         e[2].record(stream)
@@ -782,6 +799,25 @@ def measure_scene(args, torch, rc, dev, s, steps, warmup, cpu_seconds, verify, c
     # The plain call on the same scene (when the headline uses the workspace);
     # the headline path's output is kept for the bit-exact check first.
     head_out = out_t.cpu().numpy().view(np.uint16) if ws_bytes else None
+    pair = None
+    if ws_bytes:
+        # The same step as two plain calls, for reference: rc_lut_build, then
+        # rc_correct_ws (which encodes the LUT itself); 3 + 10 steps.
+        pev = []
+        for i in range(13):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            build_plain()
+            e[1].record(stream)
+            correct_ws()
+            e[2].record(stream)
+            if i >= 3:
+                pev.append(e)
+        stream.synchronize()
+        pair = {"lut_build_ms": round(statistics.mean(e[0].elapsed_time(e[1]) for e in pev), 4),
+                "rc_correct_ws_ms": round(statistics.mean(e[1].elapsed_time(e[2]) for e in pev), 4),
+                "step_ms": round(statistics.mean(e[0].elapsed_time(e[2]) for e in pev), 4),
+                "note": "rc_lut_build + rc_correct_ws back to back, 10 steps"}
     plain_ms = time_copy(correct_plain, 10) if ws_bytes else None
     rc_cp_ms = time_copy(lambda: rc.rc_stream_copy(dn_t, cp_t, 2 * px, cplan, stream))
     copy_ok = bool(torch.equal(cp_t, dn_t))
@@ -855,7 +891,7 @@ def measure_scene(args, torch, rc, dev, s, steps, warmup, cpu_seconds, verify, c
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(s.name),
-                     "kernel": ("correction: k_dense_encode + k_apply (rc_correct_ws)"
+                     "kernel": ("correction: k_apply on the build's dense encoding (rc_correct_pre)"
                                 if ws_bytes else "lut_apply (k_apply)"),
                      "algorithmic_bytes": apply_bytes,
                      "launch_ms_mean": round(apply_avg, 4),
@@ -868,6 +904,7 @@ def measure_scene(args, torch, rc, dev, s, steps, warmup, cpu_seconds, verify, c
                              "p10": round(percentile(apply_ms, 10), 4),
                              "p90": round(percentile(apply_ms, 90), 4)},
             "lut_apply_gpix_s": round(px / (apply_avg * 1e-3) / 1e9, 2),
+            "workspace_pair": pair,
             "plain_rc_correct": None if not ws_bytes else {
                 "ms_mean": round(statistics.mean(plain_ms), 4),
                 "frac_hbm": round(apply_bytes / (statistics.mean(plain_ms) * 1e-3) / 1e9 /

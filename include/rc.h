@@ -215,6 +215,38 @@ rc_status rc_correct_ws(const uint16_t* dn, const uint16_t* lut, int64_t lines, 
                         const rc_plan* plan, hipStream_t stream);
 
 /*
+ * LUT generation (§I "LUT generation") that also leaves the LUT's dense
+ * encoding in a workspace: the same LUT as rc_lut_build, bit for bit, and
+ * the same workspace contents rc_correct_ws writes for that LUT, in one
+ * kernel (one wave per LUT row evaluates it, stores it, and encodes its
+ * 64-level blocks), so that rc_correct_pre can correct without reading the
+ * LUT back. For 2048 <= levels <= 8192 (rc_correct_ws_bytes(...) > 0).
+ *   coeffs, lut   as rc_lut_build.
+ *   ws, ws_bytes  device workspace, 256-byte aligned, ws_bytes >=
+ *                 rc_correct_ws_bytes(detectors, bands, levels); caller-owned,
+ *                 contents overwritten, must not overlap coeffs or lut.
+ * Allocates nothing, never synchronises (capturable).
+ * Errors: as rc_lut_build; RC_EINVAL also for levels outside [2048, 8192]
+ * and for a missing, misaligned, short or overlapping workspace.
+ */
+rc_status rc_lut_build_ws(const double* coeffs, int32_t bands, int32_t detectors, int32_t levels,
+                          uint16_t* lut, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * rc_correct_ws without its encoding pass (§I "Image Correction"): the
+ * workspace must already hold the dense encoding of this lut, as
+ * rc_lut_build_ws or rc_correct_ws left it (and nothing may have changed the
+ * LUT or the workspace since); the result is then rc_correct's, bit for bit.
+ * The tiles read the encoded blocks, and the LUT only for levels of blocks
+ * the dense form cannot hold. Arguments, plan, ordering and errors as
+ * rc_correct_ws; RC_EINVAL also for levels outside [2048, 8192]. A workspace
+ * that does not hold the encoding of `lut` gives wrong output, not an error.
+ */
+rc_status rc_correct_pre(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                         int32_t bands, int32_t levels, uint16_t* out, const void* ws,
+                         size_t ws_bytes, const rc_plan* plan, hipStream_t stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the
  * correction of rc_correct_ws with the library's own scratch instead of a

@@ -188,6 +188,11 @@ _lib.rc_correct_ws_bytes.restype = ctypes.c_size_t
 _lib.rc_correct_ws.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t,
                                ctypes.POINTER(Plan), _vp]
 _lib.rc_correct_ws.restype = ctypes.c_int
+_lib.rc_lut_build_ws.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.rc_lut_build_ws.restype = ctypes.c_int
+_lib.rc_correct_pre.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t,
+                                ctypes.POINTER(Plan), _vp]
+_lib.rc_correct_pre.restype = ctypes.c_int
 _lib.rc_correct_noalloc.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp]
 _lib.rc_correct_noalloc.restype = ctypes.c_int
 NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -268,6 +273,20 @@ def rc_correct_ws(dn, lut, lines, detectors, bands, levels, out, ws, ws_bytes, p
     _check(_lib.rc_correct_ws(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out),
                               _ptr(ws), ws_bytes, ctypes.byref(plan) if plan is not None else None,
                               _stream(stream)), "rc_correct_ws")
+
+
+def rc_lut_build_ws(coeffs, bands, detectors, levels, lut, ws, ws_bytes, stream=None):
+    """rc_lut_build that also leaves the LUT's dense encoding in ws (see rc.h)."""
+    _check(_lib.rc_lut_build_ws(_ptr(coeffs), bands, detectors, levels, _ptr(lut), _ptr(ws),
+                                ws_bytes, _stream(stream)), "rc_lut_build_ws")
+
+
+def rc_correct_pre(dn, lut, lines, detectors, bands, levels, out, ws, ws_bytes, plan=None,
+                   stream=None):
+    """rc_correct_ws with ws already holding the LUT's encoding (see rc.h)."""
+    _check(_lib.rc_correct_pre(_ptr(dn), _ptr(lut), lines, detectors, bands, levels, _ptr(out),
+                               _ptr(ws), ws_bytes, ctypes.byref(plan) if plan is not None else None,
+                               _stream(stream)), "rc_correct_pre")
 
 
 def rc_correct_noalloc(dn, lut, lines, detectors, bands, levels, out, stream=None):

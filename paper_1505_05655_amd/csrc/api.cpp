@@ -438,7 +438,8 @@ namespace {
 
 rc_status run_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
                       int32_t bands, int32_t levels, uint16_t* out, const rc_plan* forced,
-                      hipStream_t stream, void* ws = nullptr, size_t ws_bytes = 0) {
+                      hipStream_t stream, void* ws = nullptr, size_t ws_bytes = 0,
+                      bool pre_encoded = false) {
     bool empty = false;
     rc_status st = validate_correct(dn, lut, lines, detectors, bands, levels, out, &empty);
     if (st != RC_OK || empty) return st;
@@ -480,8 +481,10 @@ rc_status run_correct(const uint16_t* dn, const uint16_t* lut, int64_t lines, in
     p.out = out;
     p.lut_vec = (levels % 8 == 0 && ((uintptr_t)lut & 15u) == 0) ? 1 : 0;
     if (use_ws) {
-        hipError_t e = launch_dense_encode(lut, bands, detectors, levels, planes, heads, stream);
-        if (e != hipSuccess) return hip_fail(e);
+        if (!pre_encoded) {
+            hipError_t e = launch_dense_encode(lut, bands, detectors, levels, planes, heads, stream);
+            if (e != hipSuccess) return hip_fail(e);
+        }
         p.pre_planes = planes;
         p.pre_heads = heads;
     }
@@ -562,6 +565,42 @@ rc_status rc_correct_ws(const uint16_t* dn, const uint16_t* lut, int64_t lines, 
                         const rc_plan* plan, hipStream_t stream) {
     if (ws_path(levels) && detectors > 0 && bands > 0 && lines > 0 && !ws) return RC_EINVAL;
     return run_correct(dn, lut, lines, detectors, bands, levels, out, plan, stream, ws, ws_bytes);
+}
+
+rc_status rc_correct_pre(const uint16_t* dn, const uint16_t* lut, int64_t lines, int32_t detectors,
+                         int32_t bands, int32_t levels, uint16_t* out, const void* ws,
+                         size_t ws_bytes, const rc_plan* plan, hipStream_t stream) {
+    if (!ws_path(levels)) return RC_EINVAL;
+    if (detectors > 0 && bands > 0 && lines > 0 && !ws) return RC_EINVAL;
+    return run_correct(dn, lut, lines, detectors, bands, levels, out, plan, stream,
+                       const_cast<void*>(ws), ws_bytes, true);
+}
+
+rc_status rc_lut_build_ws(const double* coeffs, int32_t bands, int32_t detectors, int32_t levels,
+                          uint16_t* lut, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (bands < 0 || detectors < 0 || !ws_path(levels)) return RC_EINVAL;
+    int64_t rows = 0, entries = 0, cbytes = 0, lbytes = 0;
+    if (!mul_ok(bands, detectors, &rows) || !mul_ok(rows, levels, &entries) ||
+        !mul_ok(entries, 2, &lbytes) || !mul_ok(rows, 32, &cbytes))
+        return RC_EINVAL;
+    if (rows == 0) return RC_OK;
+    if (!coeffs || !lut || !ws) return RC_EINVAL;
+    if (((uintptr_t)coeffs & 7u) || ((uintptr_t)lut & 1u) || ((uintptr_t)ws & 255u))
+        return RC_EINVAL;
+    const size_t need = dense_ws_bytes(detectors, bands, levels);
+    if (ws_bytes < need) return RC_EINVAL;
+    if (overlaps(coeffs, (size_t)cbytes, lut, (size_t)lbytes) ||
+        overlaps(ws, need, coeffs, (size_t)cbytes) || overlaps(ws, need, lut, (size_t)lbytes))
+        return RC_EINVAL;
+    int dev = 0;
+    if (!current_device(&dev)) return RC_EHIP;
+    // The split run_correct uses: planes from byte 0, headers from the next
+    // 256-byte boundary after them.
+    const size_t n = (size_t)rows * (size_t)((levels + 63) / 64);
+    uint64_t* planes = (uint64_t*)ws;
+    int16_t* heads = (int16_t*)((char*)ws + ((n * 8 + 255) & ~(size_t)255));
+    hipError_t e = launch_lut_build_ws(coeffs, rows, detectors, levels, lut, planes, heads, stream);
+    return e == hipSuccess ? RC_OK : hip_fail(e);
 }
 
 rc_status rc_plan_for(int64_t lines, int32_t detectors, int32_t bands, int32_t levels,

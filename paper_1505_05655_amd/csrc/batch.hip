@@ -213,6 +213,41 @@ __global__ __launch_bounds__(256) void k_batch_encode(const BatchReq* __restrict
     }
 }
 
+// rc_lut_build_ws: one wave per LUT row of one scene (grid-stride), the row
+// evaluated, stored and encoded as k_batch_encode does for a batch request;
+// the encoding goes to the [band][block][detector] layout rc_correct_ws
+// uses, so its tiles can stage it without an encoding pass.
+__global__ __launch_bounds__(256) void k_lut_build_ws(const double* __restrict__ coeffs,
+                                                      int64_t rows, int32_t detectors,
+                                                      int32_t levels, uint16_t* lut,
+                                                      int32_t lut_vec, uint64_t* planes,
+                                                      int16_t* heads) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t w0 = __builtin_amdgcn_readfirstlane(
+        (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int NB = (levels + 63) >> 6;
+    for (int64_t w = w0; w < rows; w += waves) {
+        const int64_t b = w / detectors;
+        const int64_t d = w - b * detectors;
+        const double* a = coeffs + w * 4;
+        const size_t o = (size_t)b * (size_t)NB * (size_t)detectors + (size_t)d;
+        encode_row_wave(levels, RowFromCoeffs{a[0], a[1], a[2], a[3], (double)levels},
+                        lut + w * (int64_t)levels, lut_vec != 0, planes + o, heads + o,
+                        (size_t)detectors);
+    }
+}
+
+hipError_t launch_lut_build_ws(const double* coeffs, int64_t rows, int32_t detectors,
+                               int32_t levels, uint16_t* lut, uint64_t* planes, int16_t* heads,
+                               hipStream_t stream) {
+    const int vec = (levels % 8 == 0 && ((uintptr_t)lut & 15u) == 0) ? 1 : 0;
+    int64_t blocks = (rows + 3) / 4;  // one wave per row
+    if (blocks > (int64_t)1 << 20) blocks = (int64_t)1 << 20;  // grid-stride beyond this
+    hipLaunchKernelGGL(k_lut_build_ws, dim3((unsigned)blocks), dim3(256), 0, stream, coeffs, rows,
+                       detectors, levels, lut, vec, planes, heads);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_lut_build_batch(const BatchReq* __restrict__ reqs,
                                                          const int64_t* __restrict__ prefix,
                                                          int32_t nreq, int64_t total) {

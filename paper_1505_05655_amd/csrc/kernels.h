@@ -50,6 +50,12 @@ hipError_t launch_dense_encode(const uint16_t* lut, int32_t bands, int32_t detec
                                int32_t levels, uint64_t* planes, int16_t* heads,
                                hipStream_t stream);
 
+// LUT build that also writes each row's dense encoding ([bands][blocks]
+// [detectors] planes and heads, as launch_dense_encode): one wave per row.
+hipError_t launch_lut_build_ws(const double* coeffs, int64_t rows, int32_t detectors,
+                               int32_t levels, uint16_t* lut, uint64_t* planes, int16_t* heads,
+                               hipStream_t stream);
+
 // lut_build: one thread per 8 consecutive levels of one LUT row.
 hipError_t launch_lut_build(const double* coeffs, int64_t rows, int32_t levels, uint16_t* lut,
                             hipStream_t stream);

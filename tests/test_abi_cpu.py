@@ -67,6 +67,33 @@ def test_lut_build_empty_is_noop():
     assert L.rc_lut_build(None, 3, 0, 1024, None, None) == rc.RC_OK
 
 
+WS4096 = 3 * 64 * 6000 * 10  # rc_correct_ws_bytes(6000, 3, 4096)
+WSA = FAKE * 4096  # past the 147 MB LUT at FAKE * 64 and the coefficients at FAKE
+
+
+@pytest.mark.parametrize("args", [
+    (FAKE, 3, 6000, 1024, FAKE * 64, WSA, WS4096),      # levels below the workspace range
+    (FAKE, 3, 6000, 8256, FAKE * 64, WSA, WS4096),      # levels above it
+    (None, 3, 6000, 4096, FAKE * 64, WSA, WS4096),      # NULL coeffs
+    (FAKE, 3, 6000, 4096, None, WSA, WS4096),           # NULL lut
+    (FAKE, 3, 6000, 4096, FAKE * 64, None, WS4096),             # NULL workspace
+    (FAKE, 3, 6000, 4096, FAKE * 64, WSA + 16, WS4096),  # workspace not 256-byte aligned
+    (FAKE, 3, 6000, 4096, FAKE * 64, WSA, WS4096 - 1),  # workspace too short
+    (FAKE, 3, 6000, 4096, FAKE * 64, FAKE * 64, WS4096),        # workspace overlaps the LUT
+    (FAKE, -3, 6000, 4096, FAKE * 64, WSA, WS4096),     # negative bands
+])
+def test_lut_build_ws_rejects(args):
+    assert L.rc_lut_build_ws(*args, None) == rc.RC_EINVAL
+
+
+def test_correct_pre_rejects():
+    """Levels outside the workspace range, and a missing workspace."""
+    assert L.rc_correct_pre(FAKE, FAKE * 64, 4, 4, 1, 1024, FAKE * 128, FAKE * 1024, 1 << 20,
+                            None, None) == rc.RC_EINVAL
+    assert L.rc_correct_pre(FAKE, FAKE * 64, 4, 4, 1, 4096, FAKE * 128, None, 1 << 20,
+                            None, None) == rc.RC_EINVAL
+
+
 BIG = 1 << 24
 
 

@@ -77,6 +77,61 @@ def test_ws_matches_oracle(o, shape, rows):
         assert np.array_equal(out.host(), want), f"plan {plan}"
 
 
+WS_SHAPES = [s for s in SHAPES if 2048 <= s[3] <= 8192]
+
+
+@pytest.mark.parametrize("shape", WS_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("rows", ["calibration", "clamped", "unpackable"])
+def test_build_ws_then_pre(o, shape, rows):
+    """rc_lut_build_ws writes the oracle's LUT and the encoding rc_correct_ws
+    makes of it (headers equal everywhere, planes wherever the header marks
+    an encoded block); rc_correct_pre then gives the oracle's image, with the
+    library's plan and with forced dense plans."""
+    B, N, D, L = shape
+    coeffs, dn = case(shape, rows, B * 7 + N + D + L)
+    want_lut = o.lut_build(coeffs, L)
+    want = o.correct(dn, want_lut)
+    need = rc.rc_correct_ws_bytes(D, B, L)
+    n = B * -(-L // 64) * D
+    hoff = (n * 8 + 255) // 256 * 256
+    dn_t = to_dev_u16(dn)
+    lut_g = Guarded((B, D, L))
+    ws = torch.full((need // 2 + 128,), 0x3C3C, dtype=torch.int16, device=dev())
+    rc.rc_lut_build_ws(to_dev_f64(coeffs), B, D, L, lut_g.t, ws, need)
+    torch.cuda.synchronize()
+    lut_g.check_pads()
+    assert np.array_equal(lut_g.host(), want_lut)
+    ws_ref = torch.full_like(ws, 0x3C3C)
+    tmp = torch.empty_like(dn_t)
+    rc.rc_correct_ws(dn_t, lut_g.t, N, D, B, L, tmp, ws_ref, need)
+    torch.cuda.synchronize()
+    got_b = ws.cpu().numpy().view(np.uint8)
+    ref_b = ws_ref.cpu().numpy().view(np.uint8)
+    heads = got_b[hoff:hoff + 2 * n].view(np.int16)
+    assert np.array_equal(heads, ref_b[hoff:hoff + 2 * n].view(np.int16))
+    enc = heads != -32768
+    assert np.array_equal(got_b[:8 * n].view(np.uint64)[enc], ref_b[:8 * n].view(np.uint64)[enc])
+    if rows == "unpackable":
+        assert not enc.all()
+    plans = [None]
+    for strip, vec, threads, unroll, chunk, strips in ((256, 4, 512, 8, N, 0),
+                                                       (128, 8, 256, 4, 17, 0),
+                                                       (256, 4, 256, 8, 33, 3)):
+        if D % vec or -(-L // 64) * strip * 10 > 160 * 1024:
+            continue
+        if strips and (strips > D // vec or vec * -(-(D // vec) // strips) > strip):
+            continue
+        plans.append(rc.Plan(path=rc.RC_PATH_DENSE, strip=strip, vec=vec, threads=threads,
+                             unroll=unroll, chunk_lines=chunk, xcd_remap=1, nontemporal=0,
+                             strips=strips))
+    for plan in plans:
+        out = Guarded((B, N, D))
+        rc.rc_correct_pre(dn_t, lut_g.t, N, D, B, L, out.t, ws, need, plan)
+        torch.cuda.synchronize()
+        out.check_pads()
+        assert np.array_equal(out.host(), want), f"plan {plan}"
+
+
 def test_ws_rejects():
     B, N, D, L = 1, 8, 64, 4096
     dn = torch.zeros((B, N, D), dtype=torch.int16, device=dev())
