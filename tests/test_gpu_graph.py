@@ -71,3 +71,48 @@ def test_graph_replays_match_oracle():
         assert np.array_equal(out.cpu().numpy().view(np.uint16), want), k
         assert np.array_equal(rgb.cpu().numpy().view(np.uint16), o.demosaic(raw)), k
         assert np.array_equal(rgb_g.cpu().numpy().view(np.uint16), o.demosaic_gradient(raw)), k
+
+
+def test_graph_build_ws_pair_replays_match_oracle():
+    """rc_lut_build_ws + rc_correct_pre (long LUT rows, the encoding passed
+    through the workspace) captured once and replayed with new coefficients
+    and images written eagerly between replays."""
+    dev = torch.device("cuda:0")
+    o = oracle.get()
+    B, N, D, L = 2, 97, 300, 4096
+    need = rc.rc_correct_ws_bytes(D, B, L)
+    assert need > 0
+    c_s = torch.empty((B, D, 4), dtype=torch.float64, device=dev)
+    dn_s = torch.empty((B, N, D), dtype=torch.int16, device=dev)
+    lut = torch.empty((B, D, L), dtype=torch.int16, device=dev)
+    out = torch.empty_like(dn_s)
+    ws = torch.empty((need // 2 + 128,), dtype=torch.int16, device=dev)
+
+    def load(k):
+        c = gen.coeffs(gen.BASE_SEED, 51, k, gen.COEF_CUBIC, B, D)
+        dn = gen.dn(gen.BASE_SEED, 51, k, gen.DN_SCENE12, B, N, D)
+        c_s.copy_(torch.from_numpy(c))
+        dn_s.copy_(torch.from_numpy(dn.view(np.int16)))
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        return c, dn
+
+    s = torch.cuda.Stream(device=dev)
+
+    def work():
+        rc.rc_lut_build_ws(c_s, B, D, L, lut, ws, need, s)
+        rc.rc_correct_pre(dn_s, lut, N, D, B, L, out, ws, need, None, s)
+
+    load(0)
+    work()
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        work()
+    for k in range(1, 4):
+        c, dn = load(k)
+        g.replay()
+        torch.cuda.synchronize()
+        want_lut = o.lut_build(c, L)
+        assert np.array_equal(lut.cpu().numpy().view(np.uint16), want_lut), k
+        assert np.array_equal(out.cpu().numpy().view(np.uint16), o.correct(dn, want_lut)), k
