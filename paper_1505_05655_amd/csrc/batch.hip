@@ -106,25 +106,49 @@ __device__ __forceinline__ void encode_row_wave(int L, Src src, uint16_t* dst, b
         // Steps t = 8q + k (entry t+1 minus entry t) inside the block.
         const int nxt = dpp_move<kDppRowShl1>(e[0]);  // lane q + 1's first entry (q < 7)
         int mn = kBig, mx = -kBig, smin = kBig, smax = -kBig, first = 64;
+        bool sat = false;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int t = (q << 3) + k;
-            const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
-            if (t + 1 < cnt) {
-                mn = min(mn, eb - ea);
-                mx = max(mx, eb - ea);
-                if (eb != 0 && ea != top) {
-                    smin = min(smin, eb - ea);
-                    smax = max(smax, eb - ea);
+        for (int k = 0; k < 8; ++k) sat |= (e[k] == 0) | (e[k] == top);
+        if (!__any(sat)) {
+            // No entry of the wave's pass is 0 or L-1 (entries past the row
+            // read as 0, so only whole blocks get here): every step is
+            // unsaturated, the saturation-aware extrema equal the plain
+            // ones and no block starts with a run of 0.
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int t = (q << 3) + k;
+                const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
+                if (t + 1 < cnt) {
+                    mn = min(mn, eb - ea);
+                    mx = max(mx, eb - ea);
                 }
-                if (ea == 0 && eb != 0) first = min(first, t + 1);
             }
+            mn = group8_min(mn);
+            mx = group8_max(mx);
+            smin = mn;
+            smax = mx;
+            first = min(first, max(cnt, 0));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int t = (q << 3) + k;
+                const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
+                if (t + 1 < cnt) {
+                    mn = min(mn, eb - ea);
+                    mx = max(mx, eb - ea);
+                    if (eb != 0 && ea != top) {
+                        smin = min(smin, eb - ea);
+                        smax = max(smax, eb - ea);
+                    }
+                    if (ea == 0 && eb != 0) first = min(first, t + 1);
+                }
+            }
+            mn = group8_min(mn);
+            mx = group8_max(mx);
+            smin = group8_min(smin);
+            smax = group8_max(smax);
+            first = min(group8_min(first), max(cnt, 0));
         }
-        mn = group8_min(mn);
-        mx = group8_max(mx);
-        smin = group8_min(smin);
-        smax = group8_max(smax);
-        first = min(group8_min(first), max(cnt, 0));
         const int e0 = group8_max(q == 0 ? e[0] : -1);  // entries are >= 0
         int last = -1;  // entry cnt - 1, held by one lane of the group
 #pragma unroll
