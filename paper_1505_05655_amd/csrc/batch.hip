@@ -105,30 +105,39 @@ __device__ __forceinline__ void encode_row_wave(int L, Src src, uint16_t* dst, b
         }
         // Steps t = 8q + k (entry t+1 minus entry t) inside the block.
         const int nxt = dpp_move<kDppRowShl1>(e[0]);  // lane q + 1's first entry (q < 7)
-        int mn = kBig, mx = -kBig, smin = kBig, smax = -kBig, first = 64;
+        const int e0 = group8_max(q == 0 ? e[0] : -1);  // entries are >= 0
         bool sat = false;
 #pragma unroll
         for (int k = 0; k < 8; ++k) sat |= (e[k] == 0) | (e[k] == top);
+        bool ok = true;
+        int s = 0, u0 = e0;
+        uint32_t lo8 = 0;
         if (!__any(sat)) {
-            // No entry of the wave's pass is 0 or L-1 (entries past the row
-            // read as 0, so only whole blocks get here): every step is
-            // unsaturated, the saturation-aware extrema equal the plain
-            // ones and no block starts with a run of 0.
+            // No entry of the wave's pass is 0 or L-1. Entries past the row
+            // read as 0, so every block of the pass is whole, and none is
+            // saturated: each is the unsaturated kind below, or not
+            // encodable (a negative step), with the plain step extrema.
+            int mn = kBig, mx = -kBig;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const int t = (q << 3) + k;
                 const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
-                if (t + 1 < cnt) {
+                if ((q << 3) + k + 1 < cnt) {
                     mn = min(mn, eb - ea);
                     mx = max(mx, eb - ea);
                 }
             }
             mn = group8_min(mn);
             mx = group8_max(mx);
-            smin = mn;
-            smax = mx;
-            first = min(first, max(cnt, 0));
+            s = max(0, mx - 1);
+            ok = s <= 1 && mn >= s;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
+                const int bit = (q << 3) + k + 1 < cnt ? eb - ea - s : 0;
+                lo8 |= (uint32_t)(bit & 1) << k;
+            }
         } else {
+            int mn = kBig, mx = -kBig, smin = kBig, smax = -kBig, first = 64;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int t = (q << 3) + k;
@@ -148,39 +157,36 @@ __device__ __forceinline__ void encode_row_wave(int L, Src src, uint16_t* dst, b
             smin = group8_min(smin);
             smax = group8_max(smax);
             first = min(group8_min(first), max(cnt, 0));
-        }
-        const int e0 = group8_max(q == 0 ? e[0] : -1);  // entries are >= 0
-        int last = -1;  // entry cnt - 1, held by one lane of the group
+            int last = -1;  // entry cnt - 1, held by one lane of the group
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if ((q << 3) + k == cnt - 1) last = e[k];
-        last = group8_max(last);
-        bool ok = true;
-        int s = 0, u0 = e0, kind = 0;  // 0 constant, 1 unsaturated, 2 transition
-        if (cnt > 1 && mn < 0) {
-            ok = false;
-        } else if (cnt <= 1 || e0 == top || last == 0) {
-            kind = 0;
-        } else if (e0 != 0 && last != top) {
-            kind = 1;
-            s = max(0, mx - 1);
-            ok = s <= 1 && mn >= s;
-        } else {
-            kind = 2;
-            s = max(0, smax - 1);
-            ok = s <= 1 && smin >= s;
-            if (e0 == 0) u0 = -(s + 1) * (first - 1);
-        }
-        uint32_t lo8 = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
-            int bit = 0;
-            if ((q << 3) + k + 1 < cnt) {
-                if (kind == 1) bit = eb - ea - s;
-                if (kind == 2) bit = (eb != 0 && ea != top) ? eb - ea - s : 1;
+            for (int k = 0; k < 8; ++k)
+                if ((q << 3) + k == cnt - 1) last = e[k];
+            last = group8_max(last);
+            int kind = 0;  // 0 constant, 1 unsaturated, 2 transition
+            if (cnt > 1 && mn < 0) {
+                ok = false;
+            } else if (cnt <= 1 || e0 == top || last == 0) {
+                kind = 0;
+            } else if (e0 != 0 && last != top) {
+                kind = 1;
+                s = max(0, mx - 1);
+                ok = s <= 1 && mn >= s;
+            } else {
+                kind = 2;
+                s = max(0, smax - 1);
+                ok = s <= 1 && smin >= s;
+                if (e0 == 0) u0 = -(s + 1) * (first - 1);
             }
-            lo8 |= (uint32_t)(bit & 1) << k;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
+                int bit = 0;
+                if ((q << 3) + k + 1 < cnt) {
+                    if (kind == 1) bit = eb - ea - s;
+                    if (kind == 2) bit = (eb != 0 && ea != top) ? eb - ea - s : 1;
+                }
+                lo8 |= (uint32_t)(bit & 1) << k;
+            }
         }
         // Bit t+1 of the block word = b_t: this lane's bits start at 8q+1.
         const uint64_t mine = (uint64_t)lo8 << ((q << 3) + 1);
