@@ -130,12 +130,14 @@ __device__ __forceinline__ void encode_row_wave(int L, Src src, uint16_t* dst, b
             mx = group8_max(mx);
             s = max(0, mx - 1);
             ok = s <= 1 && mn >= s;
+            // Bit k is the parity of step 8q + k minus s: the low bits of its
+            // two entries and of s, XORed (the block is whole, so only step
+            // 63 of lane q = 7 does not exist).
+            uint32_t par = 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int ea = e[k], eb = k < 7 ? e[k + 1] : nxt;
-                const int bit = (q << 3) + k + 1 < cnt ? eb - ea - s : 0;
-                lo8 |= (uint32_t)(bit & 1) << k;
-            }
+            for (int k = 0; k < 8; ++k) par |= ((uint32_t)e[k] & 1u) << k;
+            par |= ((uint32_t)nxt & 1u) << 8;
+            lo8 = (par ^ (par >> 1) ^ (s ? 0xFFu : 0u)) & (q == 7 ? 0x7Fu : 0xFFu);
         } else {
             int mn = kBig, mx = -kBig, smin = kBig, smax = -kBig, first = 64;
 #pragma unroll
